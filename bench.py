@@ -1,0 +1,296 @@
+#!/usr/bin/env python3
+"""Benchmark: configs*sym-images/s for log psi + E_loc on one MI355X.
+
+Workload (default): the 6x6 J1-J2 lattice (J2/J1 = 0.5), one complex RBM with
+M = 72 (alpha = 2) in FP32, projected on the 288 space-group images,
+4096 chains x 64 samples = 262144 configurations resident in HBM.  A step is
+one nqs_eloc call (theta GEMM + log 2cosh/LSE epilogue + bond-exchange
+products) over the whole batch; value = S * K * G / step time.
+
+Printed as ONE JSON line, with
+  roofline     -- the dominant kernel (eloc_bonds), achieved algorithmic
+                  TFLOP/s (13 real flops per exchange factor) against the
+                  FP32 vector peak, from HIP events recorded live around each
+                  launch on the call's stream;
+  cpu_baseline -- the FP64 oracle timed on this host's cores on a bounded
+                  sample of the same configurations;
+  errors       -- log psi / E_loc errors of the timed path vs the oracle;
+  legs         -- the other rows of the hot path (backward, two-hop Lanczos
+                  moments, split-BF16 vs FP32 at 8x8, sampling, SR), timed.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+FLOPS_PER_FACTOR = 13             # P <- P (1 + t T): complex mul, +1, complex mul
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def n_antiparallel(spins, bonds):
+    return (spins[:, bonds[:, 0]] != spins[:, bonds[:, 1]]).sum(axis=1)
+
+
+# ------------------------------------------------------------- CPU baseline
+
+def _oracle_chunk(args):
+    name, params, spins = args
+    from threadpoolctl import threadpool_limits
+    import oracle
+    from workloads import WORKLOADS
+    om = oracle.Model.from_workload(WORKLOADS[name])
+    with threadpool_limits(1):          # one BLAS thread per worker process
+        lp = oracle.logpsi(om, params, spins)
+        el = oracle.eloc_direct(om, params, spins)
+    return lp, el
+
+
+def cpu_baseline(name, params, spins, budget_s=20.0):
+    """Time the oracle's log psi + E_loc on a bounded sample on all host cores."""
+    from workloads import WORKLOADS
+    w = WORKLOADS[name]
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))
+    # calibrate on two configurations (after a warm-up), then size the sample to ~budget_s
+    _oracle_chunk((name, params, spins[:1]))
+    t0 = time.perf_counter()
+    _oracle_chunk((name, params, spins[:2]))
+    per = (time.perf_counter() - t0) / 2
+    n = int(max(cores, min(len(spins), 0.7 * budget_s * cores / max(per, 1e-3))))
+    n = max(cores, (n // cores) * cores)
+    log(f"cpu baseline: {per * 1e3:.1f} ms per configuration on one core; "
+        f"timing {n} configurations on {cores} worker processes")
+    chunks = [(name, params, spins[i::cores][: n // cores]) for i in range(cores)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        outs = pool.map(_oracle_chunk, chunks)
+    dt = time.perf_counter() - t0
+    return {"value": n * w.n_rbm * w.G / dt, "unit": "configs*sym-images/s", "cores": cores,
+            "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"{n} of the benchmark's configurations, FP64 NumPy log psi + E_loc by "
+                      f"direct re-evaluation, {cores} worker processes, {dt:.1f} s"}
+
+
+# ------------------------------------------------------------------- GPU legs
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def errors_vs_oracle(name, params, spins_np, lp_gpu, el_gpu, n=12):
+    import oracle
+    from workloads import WORKLOADS
+    om = oracle.Model.from_workload(WORKLOADS[name])
+    idx = np.random.default_rng(0).choice(len(spins_np), n, replace=False)
+    lp = oracle.logpsi(om, params, spins_np[idx])
+    el = oracle.eloc_direct(om, params, spins_np[idx])
+    d = lp_gpu[idx] - lp
+    d = d.real + 1j * np.angle(np.exp(1j * d.imag))
+    return {"checked": int(n),
+            "max_abs_dlogpsi": float(np.abs(d).max()),
+            "max_rel_deloc": float((np.abs(el_gpu[idx] - el) / np.maximum(1, np.abs(el))).max()),
+            "rel_err_mean_eloc": float(abs(el_gpu[idx].mean() - el.mean()) / abs(el.mean()))}
+
+
+def leg_lanczos(steps=2):
+    """Two-hop e2 + FP64 moments on the 6x6 Lanczos workload (8192 samples)."""
+    import torch
+    from paper_2206_14307_amd import NQS
+    from workloads import WORKLOADS, draw_params, random_sz0_spins_fast
+    w = WORKLOADS["6x6_fp32_lanczos"]
+    m = NQS.from_workload(w)
+    m.set_params(torch.from_numpy(draw_params(w).reshape(-1)))
+    S = w.n_chains * w.n_per_chain
+    sp = torch.from_numpy(random_sz0_spins_fast(w.N, S, 3003)).cuda()
+    res = {}
+    ms = timed(lambda: res.update(m.lanczos_moments(sp, exact=False, want_e1e2=False)[0]), steps, 1)
+    return {"workload": w.name, "S": S, "ms": ms,
+            "configs_per_s": S / (ms / 1e3), "h1_per_site": res["h1"] / w.N,
+            "e_p1_per_site": res["e_p1"] / w.N}
+
+
+def leg_grad(m, sp, S, G, K, steps=3):
+    import torch
+    O = torch.empty((S, m.P), dtype=m.o_dtype, device="cuda")
+    ws = m.workspace("grad", S)
+    import ctypes as C
+    from paper_2206_14307_amd.nqs import _ptr, _stream
+
+    def run():
+        m._check(m.lib.nqs_grad(m._ctx, _ptr(sp), S, _ptr(O), None, _ptr(ws), ws.numel(),
+                                _stream()), "nqs_grad")
+    ms = timed(run, steps, 1)
+    del O
+    return {"S": S, "ms": ms, "configs_sym_images_per_s": S * K * G / (ms / 1e3),
+            "O_bytes": S * m.P * (16 if m.precision == "fp64" else 8)}
+
+
+def leg_precision(name, steps=2):
+    """split-BF16 vs FP32 theta on the same spins, both against the oracle."""
+    import dataclasses
+    import torch
+    from paper_2206_14307_amd import NQS
+    from workloads import WORKLOADS, draw_params, random_sz0_spins_fast
+    out = {}
+    base = WORKLOADS[name]
+    S = 4096
+    spins = random_sz0_spins_fast(base.N, S, 4004)
+    sp = torch.from_numpy(spins).cuda()
+    for prec in ("fp32", "bf16x2"):
+        w = dataclasses.replace(base, precision=prec)
+        p = draw_params(w)
+        m = NQS.from_workload(w)
+        m.set_params(torch.from_numpy(p.reshape(-1)))
+        holder = {}
+        ms = timed(lambda: holder.update(r=m.eloc(sp)), steps, 1)
+        lp, el = holder["r"]
+        err = errors_vs_oracle(name, p, spins, lp.cpu().numpy(), el.cpu().numpy(), n=2)
+        out[prec] = {"ms": ms, "configs_sym_images_per_s": S * w.n_rbm * w.G / (ms / 1e3), **err}
+    out["workload"] = name
+    out["S"] = S
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="6x6_fp32_eloc")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the hot path is measured at "
+                                   "--gpus 1 only (the multi-GPU sharding is a design, "
+                                   "not an implementation)"}))
+        sys.exit(2)
+
+    import torch
+    import oracle
+    from paper_2206_14307_amd import NQS
+    from workloads import WORKLOADS, draw_params, random_sz0_spins_fast
+
+    w = WORKLOADS[args.workload]
+    S = w.n_chains * w.n_per_chain
+    params = draw_params(w)
+    spins_np = random_sz0_spins_fast(w.N, S, 2002)
+    # the CPU baseline runs first, in worker processes forked before any GPU use
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, params, spins_np)
+    if cpu:
+        log(f"cpu baseline done: {cpu['value']:.3g} {cpu['unit']} on {cpu['cores']} cores")
+    m = NQS.from_workload(w)
+    m.set_params(torch.from_numpy(params.reshape(-1)))
+    sp = torch.from_numpy(spins_np).cuda()
+    lp = torch.empty(S, dtype=torch.complex128, device="cuda")
+    el = torch.empty(S, dtype=torch.complex128, device="cuda")
+    ws = m.workspace("eloc", S)
+    from paper_2206_14307_amd.nqs import _ptr, _stream
+
+    def step():
+        m._check(m.lib.nqs_eloc(m._ctx, _ptr(sp), S, _ptr(lp), _ptr(el), _ptr(ws), ws.numel(),
+                                _stream()), "nqs_eloc")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    m.profile(True)
+    for k in ("theta", "lse", "eloc_bonds", "eloc_finish"):
+        m.profile_read(k, reset=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step")
+    kern = {k: m.profile_read(k, reset=True) for k in ("theta", "lse", "eloc_bonds", "eloc_finish")}
+    m.profile(False)
+
+    om = oracle.Model.from_workload(w)
+    nc = n_antiparallel(spins_np, om.lat.bonds).astype(np.int64)
+    factors_per_step = int(nc.sum()) * w.G * w.n_rbm * w.n_hidden
+    ms_bonds, n_bonds = kern["eloc_bonds"]
+    launches_per_step = n_bonds / args.steps
+    flops_per_launch = FLOPS_PER_FACTOR * factors_per_step / launches_per_step
+    avg_ms = ms_bonds / n_bonds
+    achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
+    roofline = {"kernel": "eloc_bonds", "bound": "alu", "achieved": achieved,
+                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                "avg_launch_ms": avg_ms, "launches_per_step": launches_per_step,
+                "flops_per_launch": flops_per_launch,
+                "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()}}
+
+    errs = errors_vs_oracle(args.workload, params, spins_np, lp.cpu().numpy(), el.cpu().numpy())
+    log(f"errors vs oracle: {errs}")
+    result = {
+        "metric": "configs*sym-images/s for logpsi+E_loc, 1 GPU, at stated energy error",
+        "value": S * w.n_rbm * w.G / (ms_step / 1e3),
+        "unit": "configs*sym-images/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "lattice": f"{w.L}x{w.L}", "J2": w.J2,
+                   "n_rbm": w.n_rbm, "n_hidden": w.n_hidden, "sym_images": w.G,
+                   "configs": S, "params": "N(0,0.01) complex, seed %d" % w.seed,
+                   "spins": "uniform random Sz=0 configurations, seed 2002"},
+        "roofline": roofline,
+        "errors": errs,
+    }
+    legs = {}
+    if not args.no_legs:
+        legs["grad"] = leg_grad(m, sp, S, w.G, w.n_rbm)
+        log(f"grad leg: {legs['grad']['ms']:.2f} ms")
+        legs["lanczos_two_hop"] = leg_lanczos()
+        log(f"lanczos leg: {legs['lanczos_two_hop']['ms']:.2f} ms")
+        legs["bf16x2_vs_fp32_8x8"] = leg_precision("8x8_k4_m256")
+        log("precision leg done")
+    result["legs"] = legs
+    del ws
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

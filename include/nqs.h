@@ -1,0 +1,190 @@
+/*
+ * nqs.h -- C ABI of the MI355X (gfx950) hot path for symmetry-projected RBM
+ * wave functions of the J1-J2 Heisenberg model with a p = 1 Lanczos step
+ * (arXiv:2206.14307, "Systematic improvement of neural network quantum
+ * states using a Lanczos recursion").
+ *
+ * Model (Sec. 2.1, Eq. (1)): H = J1 sum_<ij> S_i.S_j + J2 sum_<<ij>> S_i.S_j on
+ * the L x L torus, Sz = 0 sector.  Ansatz (Sec. 3.1, Eqs. (2), (6)):
+ *   psi(sigma) = sum_{k<K} sum_{g in G} chi(g) psi_s^(k)(g sigma),
+ *   psi_s^(k)(x) = exp(sum_j a_j x_j) prod_{h<M} 2 cosh(sum_j W_hj x_j + b_h),
+ * G = translations x C4v (8N elements), (g sigma)[i] = sigma[perm_g(i)],
+ * perm_g(i) = site(p . r_i + t) for g = (t, p), rotations about site 0,
+ * chi(g) = exp(-i K.t) chi_I(p) for K in {(0,0), (pi,pi)} and a 1-D irrep I.
+ *
+ * Conventions shared by every entry point
+ *  - Spins: int8 +1 / -1 encodes sigma = +1/2 / -1/2, row-major [S][N],
+ *    site i = x + L*y; rows are taken to hold exactly N/2 entries +1 (the
+ *    Sz = 0 sector).  Other rows are not rejected by the evaluation calls:
+ *    their results are meaningless, but no access leaves its buffer.
+ *  - Complex values are interleaved (re, im) pairs of double unless a
+ *    dtype is stated otherwise.
+ *  - Ownership: the caller allocates every input, output and workspace
+ *    buffer (device memory unless stated); the context owns only its
+ *    constant tables and a copy of the parameters.  No entry point
+ *    allocates device memory except nqs_create and nqs_set_params.
+ *  - Streams: work is enqueued on the given stream and returns without
+ *    waiting, except where an entry point says it synchronises.
+ *  - Errors: arguments are validated before anything is launched; on an
+ *    error nothing is launched and outputs are untouched.  No exception
+ *    crosses the ABI.  nqs_last_error() returns a message for the last
+ *    failing call on that context.
+ *  - Concurrency: calls on one context may be issued from one host thread
+ *    at a time; calls that share a workspace must be ordered on one stream.
+ */
+#ifndef NQS_H
+#define NQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NQS_OK = 0,
+    NQS_ERR_ARG = 1,          /* invalid argument or workspace too small; nothing launched */
+    NQS_ERR_DEVICE = 2,       /* a HIP runtime call failed */
+    NQS_ERR_OOM = 3,          /* the context could not allocate its tables */
+    NQS_ERR_NONFINITE = 4,    /* non-finite parameters or non-finite moments */
+    NQS_WARN_DEGENERATE = 5,  /* Lanczos: zero variance (eigenstate); e_p1 = h1, alpha = 0 */
+    NQS_ERR_NOT_PD = 6        /* SR: the Gram matrix is not positive definite */
+} nqs_status;
+
+typedef enum {
+    NQS_FP64 = 0,    /* everything in FP64 (theta GEMM on FP64 MFMA) */
+    NQS_FP32 = 1,    /* FP32 arithmetic, theta GEMM on FP32 MFMA */
+    NQS_BF16X2 = 2   /* theta GEMM on BF16 MFMA with W split into hi + lo BF16 parts,
+                        FP32 accumulation; everything else as NQS_FP32 */
+} nqs_precision;
+
+typedef enum {
+    NQS_OP_LOGPSI = 0, NQS_OP_ELOC = 1, NQS_OP_MOMENTS = 2,
+    NQS_OP_GRAD = 3, NQS_OP_SR = 4, NQS_OP_SAMPLE = 5
+} nqs_op;
+
+typedef struct {
+    int32_t L;          /* linear size: 4, 6, 8 or 10 (N = L*L sites) */
+    double J1, J2;      /* couplings of Eq. (1) */
+    int32_t kx, ky;     /* momentum K = 2 pi (kx, ky) / L: (0,0) or (L/2, L/2) */
+    int32_t irrep;      /* C4v irrep: 0 A1, 1 A2, 2 B1, 3 B2 (1-D only) */
+    int32_t n_rbm;      /* K >= 1: RBMs summed in the linear combination */
+    int32_t n_hidden;   /* M per RBM, a multiple of 8, K*M <= 4096 */
+    int32_t use_bias;   /* 1: per-RBM parameters [W | a | b]; 0: [W] (bias-free psi_s) */
+    int32_t precision;  /* nqs_precision */
+} nqs_model_desc;
+
+/* Moments and p = 1 Lanczos energy (Sec. 3.3, Eqs. (13)-(18)).  All FP64.
+ * h1 = Re<e1>, h2 = <|e1|^2>, h2_alt = Re<e2>, h3 = Re<conj(e1) e2>,
+ * c2 = <|e1-h1|^2>, c3 = Re<conj(e1-h1)(e2 - 2 h1 e1 + h1^2)>,
+ * v = sqrt(c2), r = c3 / v^3, alpha = r/2 - sqrt(r^2/4 + 1) (the printed
+ * alpha = r - sqrt(r^2+1) lacks the 1/2 of the 2x2 matrix h1 I + v[[0,1],[1,r]]),
+ * e_p1 = h1 + v alpha.  h1_err = sqrt(c2 / n) (naive standard error). */
+typedef struct {
+    int64_t n;
+    double h1, h1_im, h2, h2_alt, h3, c2, c3, v, r, alpha, e_p1, h1_err;
+    int32_t degenerate;
+} nqs_moments;
+
+typedef struct nqs_ctx nqs_ctx;
+
+/* Create a context for one model: builds the lattice, bond and space-group
+ * tables (Sec. 3.1) on the current HIP device.  Parameters start at zero.
+ * Returns NQS_ERR_ARG for an unsupported description. */
+nqs_status nqs_create(const nqs_model_desc* desc, nqs_ctx** out);
+void nqs_destroy(nqs_ctx* ctx);
+
+/* Number of complex parameters P = K * (M N + use_bias (N + M)). */
+int64_t nqs_num_params(const nqs_ctx* ctx);
+
+/* Bytes of workspace entry point `op` needs for S samples (S = n_chains for
+ * NQS_OP_SAMPLE).  Large S is processed in chunks, so the size saturates. */
+size_t nqs_workspace_bytes(const nqs_ctx* ctx, int op, int64_t S);
+
+/* Upload parameters: params_dev is device memory holding P complex values
+ * (double re, im) in the layout [K][W (M x N, row-major) | a (N) | b (M)].
+ * Derives the precision-specific copies and the per-bond tables
+ * (tanh and cosh of W_hp - W_hq, Sec. 3.1 applied to bond exchanges).
+ * Synchronises the stream.  NQS_ERR_NONFINITE if any value is NaN/Inf. */
+nqs_status nqs_set_params(nqs_ctx* ctx, const double* params_dev, hipStream_t stream);
+
+/* log psi(sigma) of Eq. (6) for S configurations: logpsi_out complex [S]
+ * (Im in (-pi, pi]).  Workspace: nqs_workspace_bytes(NQS_OP_LOGPSI, S). */
+nqs_status nqs_logpsi(nqs_ctx* ctx, const int8_t* spins, int64_t S, double* logpsi_out,
+                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Local energies E_loc(sigma) = <sigma|H|psi>/<sigma|psi> (Sec. 3.2, Eq. (10))
+ * over the antiparallel J1 and J2 bonds: eloc_out complex [S]; logpsi_out
+ * (complex [S]) is written too unless NULL.  Configurations with psi = 0
+ * (possible for non-A1 irreps) give non-finite E_loc. */
+nqs_status nqs_eloc(nqs_ctx* ctx, const int8_t* spins, int64_t S, double* logpsi_out,
+                    double* eloc_out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* e1 = E_loc and e2 = (H^2 psi)/psi per configuration (two-hop connected
+ * configurations), then the FP64 moments and p = 1 Lanczos energy
+ * (Sec. 3.3).  exact = 0: uniform weights (Monte-Carlo samples);
+ * exact = 1: Born weights |psi|^2 / sum |psi|^2 (Sec. 3.2, Eq. (9)) over the
+ * given configurations (the whole Sz = 0 sector for exact results).
+ * e1e2_out (complex [S][2]) is optional.  Writes *out and synchronises the
+ * stream.  NQS_WARN_DEGENERATE when c2 <= (8 eps max(|h1|,1))^2. */
+nqs_status nqs_lanczos_moments(nqs_ctx* ctx, const int8_t* spins, int64_t S, int exact,
+                               double* e1e2_out, nqs_moments* out, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+
+/* Log-derivatives O_k = d log psi / d theta_k (Sec. 3.2, below Eq. (12)) for
+ * every parameter in the nqs_set_params layout, summed over symmetry images:
+ * O_out [S][P] complex, in complex128 for NQS_FP64 and complex64
+ * (float re, im) otherwise.  logpsi_out (complex [S]) optional. */
+nqs_status nqs_grad(nqs_ctx* ctx, const int8_t* spins, int64_t S, void* O_out, double* logpsi_out,
+                    void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Stochastic-reconfiguration step of Eq. (12) with ridge lambda (Sec. 3.4),
+ * solved in sample space: O_bar = (O - <O>)/sqrt(S), eps = (E_loc - <E>)/sqrt(S),
+ * T = O_bar O_bar^H + lambda I (S x S, FP32 MFMA products, FP64 result),
+ * FP64 Cholesky T = L L^H, x = T^{-1} eps, dtheta = -dtau O_bar^H x.
+ * O: [S][P] as written by nqs_grad; eloc: complex [S]; dtheta_out complex [P].
+ * Synchronises the stream; NQS_ERR_NOT_PD if the factorisation fails. */
+nqs_status nqs_sr_solve(nqs_ctx* ctx, const void* O, const double* eloc, int64_t S, double lambda,
+                        double dtau, double* dtheta_out, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Pack initial configurations into chain states: chain_state [n][4] uint64
+ * = {spin bits 0..63, spin bits 64..127, proposal counter = 0, chain id}
+ * with chain ids first_chain_id + c.  spins: [n][N] int8 (Sz = 0). */
+nqs_status nqs_chain_init(nqs_ctx* ctx, const int8_t* spins, int64_t n_chains,
+                          uint64_t first_chain_id, uint64_t* chain_state, hipStream_t stream);
+
+/* Exchange Metropolis (Sec. 3.2): proposal n of a chain draws
+ * Philox4x64-10(counter (n,0,0,0), key (seed, chain id)) -> (r0, r1, r2, r3);
+ * the k-th up site (k = (r0>>11)*(N/2) >> 53) is exchanged with the k'-th
+ * down site (from r1); accept iff (r2>>11)*2^-53 < |psi'/psi|^2.  Runs n_burn
+ * proposals, then n_per_chain times: n_skip proposals and one kept sample.
+ * n_skip = 0 selects N_skip = max(1, ceil(5 P / A)) (capped at 1000) from the
+ * A accepted out of P burn-in proposals of all chains (Sec. 3.4, N_skip = 5/r).
+ * chain_state [n_chains][4] is read and updated; spins_out [n_chains*n_per_chain][N]
+ * (chain-major); acc_rate_out [n_chains] float (sampling phase); n_skip_out
+ * (device int32, optional) receives the N_skip used. */
+nqs_status nqs_sample(nqs_ctx* ctx, int64_t n_chains, int64_t n_per_chain, int32_t n_skip,
+                      int32_t n_burn, uint64_t seed, uint64_t* chain_state, int8_t* spins_out,
+                      float* acc_rate_out, int32_t* n_skip_out, void* ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/* Per-kernel timing for benchmarks.  While enabled, every kernel launch of
+ * this context is bracketed by HIP events on the call's stream.
+ * nqs_profile_read synchronises those events and returns, for kernel id
+ * `kernel` (0 theta, 1 lse, 2 eloc_bonds, 3 eloc_finish, 4 twohop,
+ * 5 twohop_finish, 6 moments, 7 grad, 8 sample, 9 sr), the summed duration
+ * in ms and the launch count since the last reset; reset = 1 clears them. */
+nqs_status nqs_profile_enable(nqs_ctx* ctx, int on);
+nqs_status nqs_profile_read(nqs_ctx* ctx, int kernel, double* ms_out, int64_t* launches_out,
+                            int reset);
+
+const char* nqs_status_str(nqs_status s);
+const char* nqs_last_error(const nqs_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NQS_H */

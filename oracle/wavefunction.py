@@ -44,9 +44,11 @@ def _lse(terms, weights):
         return m[..., 0] + np.log(s)
 
 
-def logpsi(model, params, spins, chunk=256):
+def logpsi(model, params, spins, chunk=None):
     """Projected log-amplitude log psi(sigma) for int +-1 spins [S, N]."""
     spins = np.atleast_2d(np.asarray(spins))
+    if chunk is None:   # bound the [chunk, G, K*M] complex intermediates to ~0.3 GB
+        chunk = max(1, int(2e7 // (model.G * model.n_hidden * model.n_rbm)))
     rbms = model.split(params)
     out = np.empty(spins.shape[0], dtype=np.complex128)
     for s0 in range(0, spins.shape[0], chunk):

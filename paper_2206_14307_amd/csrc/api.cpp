@@ -1,0 +1,434 @@
+// C ABI entry points (declared and documented in include/nqs.h): argument
+// validation, workspace carving, chunking over samples, kernel launches.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "nqs_internal.h"
+
+using namespace nqs;
+
+namespace {
+
+// Launch with optional event bracketing (nqs_profile_enable).
+#define NQS_RUN(ctx, kid, stream, call)   \
+  ([&]() -> hipError_t {                  \
+    prof_begin((ctx), (kid), (stream));   \
+    const hipError_t e_ = (call);         \
+    prof_end((ctx), (kid), (stream));     \
+    return e_;                            \
+  }())
+
+constexpr size_t kChunkBytes = size_t(2) << 30;   // per-chunk working set
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+nqs_status fail(nqs_ctx* c, nqs_status s, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+nqs_status hip_fail(nqs_ctx* c, hipError_t e, const char* where) {
+  return fail(c, NQS_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t real_size(const nqs_ctx* c) { return c->prec == NQS_FP64 ? 8 : 4; }
+
+// Per-sample bytes of the chunked intermediates.
+struct ChunkSizes {
+  size_t L, w, t, partial, partial2;
+};
+ChunkSizes per_sample(const nqs_ctx* c) {
+  ChunkSizes z;
+  z.L = (size_t)c->K * c->G * 16;
+  z.w = (size_t)c->K * c->G * 2 * real_size(c);
+  z.t = (size_t)c->G * c->KM * 2 * real_size(c);
+  z.partial = (size_t)(c->G / 32) * 16;
+  z.partial2 = (size_t)c->NB * (c->G / 32) * 16;
+  return z;
+}
+
+size_t chunk_bytes_per_sample(const nqs_ctx* c, int op) {
+  const ChunkSizes z = per_sample(c);
+  switch (op) {
+    case NQS_OP_LOGPSI: return z.L;
+    case NQS_OP_ELOC: return z.L + z.w + z.t + z.partial;
+    case NQS_OP_MOMENTS: return z.L + z.w + z.t + z.partial + z.partial2;
+    case NQS_OP_GRAD: return z.L + z.w + z.t;
+    default: return 0;
+  }
+}
+
+int64_t chunk_of(const nqs_ctx* c, int op, int64_t S) {
+  const size_t b = chunk_bytes_per_sample(c, op);
+  if (b == 0 || S <= 0) return std::max<int64_t>(S, 1);
+  const int64_t ch = (int64_t)std::max<size_t>(1, kChunkBytes / b);
+  return std::min<int64_t>(ch, S);
+}
+
+// Carve the workspace: full-S arrays first, then the chunk arrays.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* p) : base((char*)p) {}
+  void* take(size_t n) {
+    void* r = base ? base + off : nullptr;
+    off += align_up(n);
+    return r;
+  }
+};
+
+struct Work {
+  double* L = nullptr;
+  void* w = nullptr;
+  void* t = nullptr;
+  double* partial = nullptr;
+  double* partial2 = nullptr;
+  double* e1e2 = nullptr;
+  double* logpsi = nullptr;
+  double* result = nullptr;
+  double* lp = nullptr;            // chunk log psi scratch when the caller wants none
+  int64_t chunk = 1;
+  size_t bytes = 0;
+};
+
+Work plan(const nqs_ctx* c, int op, int64_t S, void* ws) {
+  Work wk;
+  Carve cv(ws);
+  const ChunkSizes z = per_sample(c);
+  if (op == NQS_OP_MOMENTS) {
+    wk.e1e2 = (double*)cv.take((size_t)std::max<int64_t>(S, 1) * 32);
+    wk.logpsi = (double*)cv.take((size_t)std::max<int64_t>(S, 1) * 16);
+    wk.result = (double*)cv.take(16 * 8);
+  }
+  const int64_t ch = chunk_of(c, op, S);
+  wk.chunk = ch;
+  wk.L = (double*)cv.take(z.L * ch);
+  if (op != NQS_OP_LOGPSI) {
+    wk.w = cv.take(z.w * ch);
+    wk.t = cv.take(z.t * ch);
+  }
+  if (op == NQS_OP_ELOC || op == NQS_OP_MOMENTS) wk.partial = (double*)cv.take(z.partial * ch);
+  if (op == NQS_OP_ELOC || op == NQS_OP_GRAD) wk.lp = (double*)cv.take((size_t)16 * ch);
+  if (op == NQS_OP_MOMENTS) wk.partial2 = (double*)cv.take(z.partial2 * ch);
+  wk.bytes = cv.off;
+  return wk;
+}
+
+nqs_status check_common(nqs_ctx* c, const int8_t* spins, int64_t S, void* ws, size_t ws_bytes,
+                        int op) {
+  if (!c) return NQS_ERR_ARG;
+  if (S < 0) return fail(c, NQS_ERR_ARG, "S must be >= 0");
+  if (S > 0 && !spins) return fail(c, NQS_ERR_ARG, "spins is NULL");
+  const size_t need = plan(c, op, S, nullptr).bytes;
+  if (S > 0 && (!ws || ws_bytes < need))
+    return fail(c, NQS_ERR_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
+  return NQS_OK;
+}
+
+template <typename T>
+nqs_status upload(nqs_ctx* c, T** dst, const std::vector<T>& src) {
+  if (hipMalloc((void**)dst, src.size() * sizeof(T)) != hipSuccess)
+    return fail(c, NQS_ERR_OOM, "hipMalloc of a geometry table failed");
+  if (hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(c, NQS_ERR_DEVICE, "hipMemcpy of a geometry table failed");
+  return NQS_OK;
+}
+
+void free_all(nqs_ctx* c) {
+  void* ptrs[] = {c->dev.perm, c->dev.bonds, c->dev.bond_J, c->dev.bmap, c->dev.chi,
+                  c->par.params, c->par.wfrag, c->par.bias, c->par.avec, c->par.Tpm,
+                  c->par.F, c->par.Tpair, c->par.Fpair, c->par.flag};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nqs_status_str(nqs_status s) {
+  switch (s) {
+    case NQS_OK: return "ok";
+    case NQS_ERR_ARG: return "invalid argument";
+    case NQS_ERR_DEVICE: return "device error";
+    case NQS_ERR_OOM: return "out of device memory";
+    case NQS_ERR_NONFINITE: return "non-finite value";
+    case NQS_WARN_DEGENERATE: return "degenerate Lanczos step (zero variance)";
+    case NQS_ERR_NOT_PD: return "matrix not positive definite";
+  }
+  return "unknown status";
+}
+
+const char* nqs_last_error(const nqs_ctx* c) { return c ? c->last_error.c_str() : "null context"; }
+
+int64_t nqs_num_params(const nqs_ctx* c) { return c ? c->P : -1; }
+
+size_t nqs_workspace_bytes(const nqs_ctx* c, int op, int64_t S) {
+  if (!c || S < 0) return 0;
+  if (op == NQS_OP_SR) {
+    // T (S x S complex double), O_bar (S x P complex float), eps, x, column means
+    const size_t Sz = (size_t)S;
+    return align_up(Sz * Sz * 16) + align_up(Sz * (size_t)c->P * 8) + 4 * align_up(Sz * 16) +
+           align_up((size_t)c->P * 16) + align_up(64 * 16);
+  }
+  if (op == NQS_OP_SAMPLE) {
+    const size_t n = (size_t)S;
+    return align_up(n * (size_t)c->G * c->KM * 2 * real_size(c)) +
+           align_up(n * (size_t)c->K * c->G * 2 * real_size(c)) + align_up(n * 32) + align_up(64);
+  }
+  return plan(c, op, S, nullptr).bytes;
+}
+
+nqs_status nqs_create(const nqs_model_desc* d, nqs_ctx** out) {
+  if (!d || !out) return NQS_ERR_ARG;
+  *out = nullptr;
+  nqs_ctx* c = new (std::nothrow) nqs_ctx();
+  if (!c) return NQS_ERR_OOM;
+  c->d = *d;
+  std::string err;
+  if (d->n_rbm < 1 || d->n_hidden < 8 || d->n_hidden % 8 != 0 ||
+      (int64_t)d->n_rbm * d->n_hidden > kMaxKM || d->precision < 0 || d->precision > 2 ||
+      (d->use_bias != 0 && d->use_bias != 1) || !std::isfinite(d->J1) || !std::isfinite(d->J2)) {
+    delete c;
+    return NQS_ERR_ARG;
+  }
+  if (!build_geometry(d->L, d->J1, d->J2, d->kx, d->ky, d->irrep, c->geo, err)) {
+    delete c;
+    return NQS_ERR_ARG;
+  }
+  c->L = d->L;
+  c->N = c->geo.N;
+  c->G = c->geo.G;
+  c->NB = c->geo.NB;
+  c->K = d->n_rbm;
+  c->M = d->n_hidden;
+  c->KM = c->K * c->M;
+  c->P_rbm = c->M * c->N + (d->use_bias ? c->N + c->M : 0);
+  c->P = (int64_t)c->K * c->P_rbm;
+  c->prec = d->precision;
+  c->n_htiles = c->KM / 8;
+  c->nk = c->prec == NQS_BF16X2 ? (2 * c->N + 31) / 32 : c->N / 4;
+  (void)hipGetDevice(&c->device);
+
+  nqs_status st = NQS_OK;
+  st = upload(c, &c->dev.perm, c->geo.perm);
+  std::vector<int32_t> bonds(2 * c->NB);
+  for (int b = 0; b < c->NB; ++b) {
+    bonds[2 * b] = c->geo.bond_i[b];
+    bonds[2 * b + 1] = c->geo.bond_j[b];
+  }
+  if (st == NQS_OK) st = upload(c, &c->dev.bonds, bonds);
+  if (st == NQS_OK) st = upload(c, &c->dev.bond_J, c->geo.bond_J);
+  if (st == NQS_OK) st = upload(c, &c->dev.bmap, c->geo.bmap);
+  if (st == NQS_OK) st = upload(c, &c->dev.chi, c->geo.chi);
+  const size_t rs = real_size(c);
+  const size_t frag_bytes = (size_t)c->n_htiles * c->nk * 64 * (c->prec == NQS_BF16X2 ? 16 : rs);
+  struct {
+    void** p;
+    size_t n;
+  } allocs[] = {{(void**)&c->par.params, (size_t)c->P * 16},
+                {&c->par.wfrag, frag_bytes},
+                {&c->par.bias, (size_t)c->KM * 2 * rs},
+                {&c->par.avec, (size_t)c->K * c->N * 2 * rs},
+                {&c->par.Tpm, (size_t)c->NB * 2 * c->KM * 2 * rs},
+                {&c->par.F, (size_t)c->K * c->NB * 2 * 2 * rs},
+                {(void**)&c->par.flag, 16}};
+  for (auto& a : allocs) {
+    if (st != NQS_OK) break;
+    if (hipMalloc(a.p, a.n) != hipSuccess) st = NQS_ERR_OOM;
+  }
+  if (st == NQS_OK && hipMemset(c->par.params, 0, (size_t)c->P * 16) != hipSuccess)
+    st = NQS_ERR_DEVICE;
+  if (st == NQS_OK && launch_prep(c, nullptr) != hipSuccess) st = NQS_ERR_DEVICE;
+  if (st == NQS_OK && hipDeviceSynchronize() != hipSuccess) st = NQS_ERR_DEVICE;
+  if (st != NQS_OK) {
+    free_all(c);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return NQS_OK;
+}
+
+void nqs_destroy(nqs_ctx* c) {
+  if (!c) return;
+  for (auto& ev : c->prof.ev)
+    for (auto& pr : ev) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  free_all(c);
+  delete c;
+}
+
+nqs_status nqs_set_params(nqs_ctx* c, const double* params, hipStream_t st) {
+  if (!c) return NQS_ERR_ARG;
+  if (!params) return fail(c, NQS_ERR_ARG, "params is NULL");
+  hipError_t e;
+  if ((e = hipMemsetAsync(c->par.flag, 0, 8, st)) != hipSuccess) return hip_fail(c, e, "memset");
+  if ((e = launch_check_finite(params, c->P * 2, c->par.flag, st)) != hipSuccess)
+    return hip_fail(c, e, "check_finite");
+  double flag = 0.0;
+  if ((e = hipMemcpyAsync(&flag, c->par.flag, 8, hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return hip_fail(c, e, "memcpy");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "sync");
+  if (flag != 0.0) return fail(c, NQS_ERR_NONFINITE, "parameters contain NaN or Inf");
+  if ((e = hipMemcpyAsync(c->par.params, params, (size_t)c->P * 16, hipMemcpyDeviceToDevice, st)) !=
+      hipSuccess)
+    return hip_fail(c, e, "memcpy params");
+  if ((e = launch_prep(c, st)) != hipSuccess) return hip_fail(c, e, "prep");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "sync");
+  return NQS_OK;
+}
+
+nqs_status nqs_logpsi(nqs_ctx* c, const int8_t* spins, int64_t S, double* logpsi_out, void* ws,
+                      size_t ws_bytes, hipStream_t st) {
+  nqs_status s = check_common(c, spins, S, ws, ws_bytes, NQS_OP_LOGPSI);
+  if (s != NQS_OK) return s;
+  if (S > 0 && !logpsi_out) return fail(c, NQS_ERR_ARG, "logpsi_out is NULL");
+  const Work wk = plan(c, NQS_OP_LOGPSI, S, ws);
+  for (int64_t s0 = 0; s0 < S; s0 += wk.chunk) {
+    const int64_t n = std::min(wk.chunk, S - s0);
+    const int8_t* sp = spins + s0 * c->N;
+    hipError_t e = NQS_RUN(c, K_THETA, st, launch_theta(c, sp, n, wk.L, nullptr, st));
+    if (e == hipSuccess)
+      e = NQS_RUN(c, K_LSE, st, launch_lse(c, wk.L, n, logpsi_out + 2 * s0, nullptr, st));
+    if (e != hipSuccess) return hip_fail(c, e, "logpsi launch");
+  }
+  return NQS_OK;
+}
+
+namespace {
+// theta (+t) -> LSE (+w) -> bond sums -> E_loc, one chunk.
+hipError_t eloc_chunk(nqs_ctx* c, const Work& wk, const int8_t* sp, int64_t n, double* logpsi,
+                      double* eloc, int eloc_stride, hipStream_t st) {
+  hipError_t e = NQS_RUN(c, K_THETA, st, launch_theta(c, sp, n, wk.L, wk.t, st));
+  if (e == hipSuccess) e = NQS_RUN(c, K_LSE, st, launch_lse(c, wk.L, n, logpsi, wk.w, st));
+  if (e == hipSuccess)
+    e = NQS_RUN(c, K_ELOC, st, launch_eloc_bonds(c, sp, n, wk.t, wk.w, wk.partial, st));
+  if (e == hipSuccess)
+    e = NQS_RUN(c, K_ELOC_FIN, st,
+                launch_eloc_finish(c, sp, n, wk.partial, eloc, eloc_stride, st));
+  return e;
+}
+}  // namespace
+
+nqs_status nqs_eloc(nqs_ctx* c, const int8_t* spins, int64_t S, double* logpsi_out,
+                    double* eloc_out, void* ws, size_t ws_bytes, hipStream_t st) {
+  nqs_status s = check_common(c, spins, S, ws, ws_bytes, NQS_OP_ELOC);
+  if (s != NQS_OK) return s;
+  if (S > 0 && !eloc_out) return fail(c, NQS_ERR_ARG, "eloc_out is NULL");
+  const Work wk = plan(c, NQS_OP_ELOC, S, ws);
+  for (int64_t s0 = 0; s0 < S; s0 += wk.chunk) {
+    const int64_t n = std::min(wk.chunk, S - s0);
+    double* lp = logpsi_out ? logpsi_out + 2 * s0 : wk.lp;
+    const hipError_t e = eloc_chunk(c, wk, spins + s0 * c->N, n, lp, eloc_out + 2 * s0, 2, st);
+    if (e != hipSuccess) return hip_fail(c, e, "eloc launch");
+  }
+  return NQS_OK;
+}
+
+nqs_status nqs_lanczos_moments(nqs_ctx* c, const int8_t* spins, int64_t S, int exact,
+                               double* e1e2_out, nqs_moments* out, void* ws, size_t ws_bytes,
+                               hipStream_t st) {
+  nqs_status s = check_common(c, spins, S, ws, ws_bytes, NQS_OP_MOMENTS);
+  if (s != NQS_OK) return s;
+  if (!out) return fail(c, NQS_ERR_ARG, "out is NULL");
+  if (S <= 0) return fail(c, NQS_ERR_ARG, "moments need S >= 1");
+  if (exact != 0 && exact != 1) return fail(c, NQS_ERR_ARG, "exact must be 0 or 1");
+  const Work wk = plan(c, NQS_OP_MOMENTS, S, ws);
+  hipError_t e = hipSuccess;
+  for (int64_t s0 = 0; s0 < S && e == hipSuccess; s0 += wk.chunk) {
+    const int64_t n = std::min(wk.chunk, S - s0);
+    const int8_t* sp = spins + s0 * c->N;
+    e = eloc_chunk(c, wk, sp, n, wk.logpsi + 2 * s0, wk.e1e2 + 4 * s0, 4, st);
+    if (e == hipSuccess)
+      e = NQS_RUN(c, K_TWOHOP, st, launch_twohop(c, sp, n, wk.t, wk.w, wk.partial2, st));
+    if (e == hipSuccess)
+      e = NQS_RUN(c, K_TWOHOP_FIN, st,
+                  launch_twohop_finish(c, sp, n, wk.partial2, wk.e1e2 + 4 * s0, st));
+  }
+  if (e == hipSuccess)
+    e = NQS_RUN(c, K_MOMENTS, st,
+                launch_moments(wk.e1e2, wk.logpsi, S, exact, nullptr, 0, wk.result, st));
+  if (e == hipSuccess && e1e2_out)
+    e = hipMemcpyAsync(e1e2_out, wk.e1e2, (size_t)S * 32, hipMemcpyDeviceToDevice, st);
+  double r[14];
+  if (e == hipSuccess) e = hipMemcpyAsync(r, wk.result, sizeof(r), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(c, e, "moments");
+  out->n = (int64_t)r[13];
+  out->h1 = r[0];
+  out->h1_im = r[1];
+  out->h2 = r[2];
+  out->h2_alt = r[3];
+  out->h3 = r[4];
+  out->c2 = r[5];
+  out->c3 = r[6];
+  out->v = r[7];
+  out->r = r[8];
+  out->alpha = r[9];
+  out->e_p1 = r[10];
+  out->h1_err = r[11];
+  out->degenerate = r[12] != 0.0;
+  for (int j = 0; j < 12; ++j)
+    if (!std::isfinite(r[j])) return fail(c, NQS_ERR_NONFINITE, "non-finite moments");
+  return out->degenerate ? NQS_WARN_DEGENERATE : NQS_OK;
+}
+
+nqs_status nqs_grad(nqs_ctx* c, const int8_t* spins, int64_t S, void* O_out, double* logpsi_out,
+                    void* ws, size_t ws_bytes, hipStream_t st) {
+  nqs_status s = check_common(c, spins, S, ws, ws_bytes, NQS_OP_GRAD);
+  if (s != NQS_OK) return s;
+  if (S > 0 && !O_out) return fail(c, NQS_ERR_ARG, "O_out is NULL");
+  const Work wk = plan(c, NQS_OP_GRAD, S, ws);
+  const size_t osz = (size_t)c->P * 2 * real_size(c);
+  for (int64_t s0 = 0; s0 < S; s0 += wk.chunk) {
+    const int64_t n = std::min(wk.chunk, S - s0);
+    const int8_t* sp = spins + s0 * c->N;
+    double* lp = logpsi_out ? logpsi_out + 2 * s0 : wk.lp;
+    hipError_t e = NQS_RUN(c, K_THETA, st, launch_theta(c, sp, n, wk.L, wk.t, st));
+    if (e == hipSuccess) e = NQS_RUN(c, K_LSE, st, launch_lse(c, wk.L, n, lp, wk.w, st));
+    if (e == hipSuccess)
+      e = NQS_RUN(c, K_GRAD, st,
+                  launch_grad(c, sp, n, wk.t, wk.w, (char*)O_out + (size_t)s0 * osz, st));
+    if (e != hipSuccess) return hip_fail(c, e, "grad launch");
+  }
+  return NQS_OK;
+}
+
+nqs_status nqs_profile_enable(nqs_ctx* c, int on) {
+  if (!c) return NQS_ERR_ARG;
+  c->prof.on = on != 0;
+  return NQS_OK;
+}
+
+nqs_status nqs_profile_read(nqs_ctx* c, int kernel, double* ms_out, int64_t* launches_out,
+                            int reset) {
+  if (!c || kernel < 0 || kernel >= K_COUNT) return NQS_ERR_ARG;
+  auto& ev = c->prof.ev[kernel];
+  for (auto& pr : ev) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pr.second) != hipSuccess ||
+        hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess)
+      return fail(c, NQS_ERR_DEVICE, "profile event");
+    c->prof.ms[kernel] += ms;
+    c->prof.n[kernel] += 1;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  ev.clear();
+  if (ms_out) *ms_out = c->prof.ms[kernel];
+  if (launches_out) *launches_out = c->prof.n[kernel];
+  if (reset) {
+    c->prof.ms[kernel] = 0.0;
+    c->prof.n[kernel] = 0;
+  }
+  return NQS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Device helpers shared by the gfx950 kernels: complex arithmetic on
+// (re, im) pairs, wavefront (64-lane) reductions, MFMA operand types.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace nqs {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ float fmaf_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaf_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename R> struct C2;
+template <> struct C2<float> { using type = float2; };
+template <> struct C2<double> { using type = double2; };
+template <typename R> using c2_t = typename C2<R>::type;
+
+template <typename T>
+__device__ __forceinline__ T cmul(T a, T b) {
+  T r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ T cadd(T a, T b) {
+  T r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ T cmk(decltype(T{}.x) re, decltype(T{}.x) im) {
+  T r;
+  r.x = re;
+  r.y = im;
+  return r;
+}
+
+// P <- P * (1 + t*T) written as two FMA chains (8 VALU operations); the
+// sign of the exchange is folded into T by the caller.
+template <typename R>
+__device__ __forceinline__ void mul_one_plus(R& pr, R& pi, R tr, R ti, R Tr, R Ti) {
+  const R a = fmaf_t(tr, Tr, fmaf_t(-ti, Ti, R(1)));   // 1 + Re(tT)
+  const R b = fmaf_t(tr, Ti, ti * Tr);                 // Im(tT)
+  const R nr = fmaf_t(pr, a, -(pi * b));
+  const R ni = fmaf_t(pr, b, pi * a);
+  pr = nr;
+  pi = ni;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// 16x16x4 MFMA output layouts differ by type: the FP32 form gives lane
+// (q = l/16, c = l%16) rows 4q + r (r = 0..3), the FP64 form gives rows
+// q + 4r.  A-operand rows are stored in the physical order that makes lane q
+// receive logical rows 4q .. 4q+3 in both cases.
+template <typename R>
+__host__ __device__ constexpr int logical_row(int phys) {
+  return sizeof(R) == 8 ? 4 * (phys & 3) + (phys >> 2) : phys;
+}
+
+// Make LDS writes of this wavefront visible to its other lanes.
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ int spin_at(const int8_t* row, int i) { return (int)row[i]; }
+
+}  // namespace nqs

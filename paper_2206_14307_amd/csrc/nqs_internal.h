@@ -1,0 +1,131 @@
+// Internal declarations shared by the host API and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/nqs.h"
+
+namespace nqs {
+
+constexpr int kMaxN = 100;          // L <= 10
+constexpr int kMaxKM = 4096;
+
+// Geometry of the L x L torus and its space group, built on the host at
+// nqs_create (Sec. 3.1).  Bonds: 4N, index b = kind*N + i for the J1 bonds
+// (i, i+x), (i, i+y) (kinds 0, 1) and the J2 bonds (i, i+x+y), (i, i+x-y)
+// (kinds 2, 3).
+struct Geometry {
+  int L = 0, N = 0, G = 0, NB = 0;
+  std::vector<uint8_t> perm;      // [G][N]  perm_g(i)
+  std::vector<int32_t> bond_i, bond_j;
+  std::vector<double> bond_J;     // [NB]
+  std::vector<int32_t> bmap;      // [G][NB]  2*beta + flip: pre-image of bond b under g
+  std::vector<double> chi;        // [G] (real for the supported K and irreps)
+};
+
+bool build_geometry(int L, double J1, double J2, int kx, int ky, int irrep, Geometry& geo,
+                    std::string& err);
+
+// Device-side tables owned by the context.
+struct DeviceTables {
+  uint8_t* perm = nullptr;        // [G][N]
+  int32_t* bonds = nullptr;       // [NB][2]
+  double* bond_J = nullptr;       // [NB]
+  int32_t* bmap = nullptr;        // [G][NB]
+  double* chi = nullptr;          // [G]
+};
+
+// Parameter-derived tables (rebuilt by nqs_set_params).  "R" is double for
+// NQS_FP64 and float otherwise; complex values are (re, im) pairs of R.
+struct ParamTables {
+  double* params = nullptr;       // [P] complex double, caller layout
+  void* wfrag = nullptr;          // MFMA A-operand fragments of the interleaved W
+  void* bias = nullptr;           // [K*M] complex R (zeros without bias)
+  void* avec = nullptr;           // [K][N] complex R
+  void* Tpm = nullptr;            // [NB][2][K*M] complex R: +tanh(D), -tanh(D)
+  void* F = nullptr;              // [K][NB][2] complex R: (J/2) exp(s A) prod_h cosh D
+  void* Tpair = nullptr;          // [N][N][K*M] complex R: tanh(W_h,p - W_h,q) (sampler)
+  void* Fpair = nullptr;          // [K][N][N] complex R: exp(a_p - a_q) prod_h cosh(...)
+  double* flag = nullptr;         // [1] non-finite detector
+};
+
+}  // namespace nqs
+
+namespace nqs {
+enum KernelId { K_THETA = 0, K_LSE, K_ELOC, K_ELOC_FIN, K_TWOHOP, K_TWOHOP_FIN, K_MOMENTS,
+                K_GRAD, K_SAMPLE, K_SR, K_COUNT };
+struct Profiler {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[K_COUNT];
+  double ms[K_COUNT] = {};
+  int64_t n[K_COUNT] = {};
+};
+}  // namespace nqs
+
+struct nqs_ctx {
+  nqs_model_desc d{};
+  int L = 0, N = 0, G = 0, NB = 0, K = 0, M = 0, KM = 0, P_rbm = 0;
+  int64_t P = 0;
+  int prec = 1;
+  int n_htiles = 0;               // K*M/8 hidden tiles of 8 units (16 interleaved rows)
+  int nk = 0;                     // MFMA K-steps over the site axis
+  nqs::Geometry geo;
+  nqs::DeviceTables dev;
+  nqs::ParamTables par;
+  std::string last_error;
+  int device = 0;
+  nqs::Profiler prof;
+};
+
+namespace nqs {
+// Bracket one launch with events when profiling is enabled.
+inline void prof_begin(nqs_ctx* c, int k, hipStream_t st) {
+  if (!c->prof.on) return;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return;
+  if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+  (void)hipEventRecord(a, st);
+  c->prof.ev[k].push_back({a, b});
+}
+inline void prof_end(nqs_ctx* c, int k, hipStream_t st) {
+  if (!c->prof.on || c->prof.ev[k].empty()) return;
+  (void)hipEventRecord(c->prof.ev[k].back().second, st);
+}
+}  // namespace nqs
+
+namespace nqs {
+
+// ----------------------------------------------------------------- launchers
+// All launchers enqueue on `st` and return hipGetLastError().
+hipError_t launch_prep(const nqs_ctx* c, hipStream_t st);
+hipError_t launch_check_finite(const double* p, int64_t n, double* flag, hipStream_t st);
+
+// theta = W x + b for every (sample, image), epilogue: per-(k, image)
+// L = a.x + sum_h log 2cosh(theta) (complex double [S][K][G]) and, if t_out,
+// t = tanh(theta) as complex R in layout [S][n_htiles][G][8].
+hipError_t launch_theta(const nqs_ctx* c, const int8_t* spins, int64_t S, double* Lout,
+                        void* t_out, hipStream_t st);
+// Per sample: log psi = LSE_{k,g}(log chi_g + L), w[s][k][g] = chi_g exp(L - log psi)
+// (complex R; skipped if w_out is null).
+hipError_t launch_lse(const nqs_ctx* c, const double* L, int64_t S, double* logpsi_out,
+                      void* w_out, hipStream_t st);
+// Bond-exchange sums: partial[s][tile] = sum_{b anti} (J_b/2) sum_{g in tile, k} w R.
+hipError_t launch_eloc_bonds(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
+                             const void* w, double* partial, hipStream_t st);
+hipError_t launch_eloc_finish(const nqs_ctx* c, const int8_t* spins, int64_t S,
+                              const double* partial, double* eloc_out, int eloc_stride,
+                              hipStream_t st);
+// Two-hop: partial2[s][slot][tile] for e2 (slot = index in the antiparallel list).
+hipError_t launch_twohop(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
+                         const void* w, double* partial2, hipStream_t st);
+hipError_t launch_twohop_finish(const nqs_ctx* c, const int8_t* spins, int64_t S,
+                                const double* partial2, double* e1e2, hipStream_t st);
+hipError_t launch_moments(const double* e1e2, const double* logpsi, int64_t S, int exact,
+                          double* partial, int nblocks, double* result, hipStream_t st);
+hipError_t launch_grad(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
+                       const void* w, void* O_out, hipStream_t st);
+
+}  // namespace nqs

@@ -1,0 +1,243 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every case compares element by element on the same seeded inputs: the full
+4x4 Sz = 0 sector in FP64 (exact mode), seeded 6x6 / 8x8 / 10x10 subsets in
+FP32 and split-BF16, stress parameters (std 0.3, complex, B1 and K = (pi,pi))
+and ragged / degenerate sizes.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import (TOL, max_logpsi_err, max_rel_err, max_row_rel_err, nonzero_rows,
+                     stress_params)
+from workloads import WORKLOADS, draw_params, random_sz0_spins
+
+pytestmark = pytest.mark.gpu
+
+
+def make(w, params):
+    from paper_2206_14307_amd import NQS
+    m = NQS.from_workload(w)
+    m.set_params(torch.from_numpy(params.reshape(-1)))
+    return m
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def sector16():
+    return oracle.sector_basis(16)
+
+
+# ------------------------------------------------------------------ 4x4 FP64
+
+@pytest.fixture(scope="module")
+def c1_case(sector16):
+    w = WORKLOADS["4x4_fp64_exact"]
+    p = draw_params(w)
+    om = oracle.Model.from_workload(w)
+    masks, spins = sector16
+    lp = oracle.logpsi(om, p, spins)
+    psi = np.exp(lp - lp.real.max())
+    H = oracle.hamiltonian_sector(om, masks)
+    e1 = (H @ psi) / psi
+    e2 = (H @ (H @ psi)) / psi
+    return w, p, om, spins, lp, e1, e2
+
+
+def test_logpsi_full_sector_fp64(c1_case):
+    w, p, om, spins, lp, e1, e2 = c1_case
+    m = make(w, p)
+    got = m.logpsi(cuda(spins)).cpu().numpy()
+    assert max_logpsi_err(got, lp) < TOL["fp64"]
+
+
+def test_eloc_full_sector_fp64(c1_case):
+    w, p, om, spins, lp, e1, e2 = c1_case
+    m = make(w, p)
+    glp, gel = m.eloc(cuda(spins))
+    assert max_logpsi_err(glp.cpu().numpy(), lp) < TOL["fp64"]
+    assert max_rel_err(gel.cpu().numpy(), e1) < TOL["fp64"]
+
+
+def test_exact_moments_fp64(c1_case):
+    w, p, om, spins, lp, e1, e2 = c1_case
+    m = make(w, p)
+    res, e12 = m.lanczos_moments(cuda(spins), exact=True)
+    e12 = e12.cpu().numpy()
+    assert max_rel_err(e12[:, 0], e1) < TOL["fp64"]
+    assert max_rel_err(e12[:, 1], e2) < TOL["fp64"]
+    ref = oracle.moments(e1, e2, weights=np.abs(np.exp(lp - lp.real.max())) ** 2)
+    assert res["n"] == len(spins)
+    for key in ("h1", "h2", "h2_alt", "h3"):
+        assert abs(res[key] - ref[key]) <= TOL["fp64"] * abs(ref[key]), key
+    assert abs(res["e_p1"] - ref["e_p1"]) <= TOL["fp64"] * abs(ref["h1"])
+    # c2 ~ 2e-7 h1^2 here: compare on the scale of h2, the raw second moment
+    assert abs(res["c2"] - ref["c2"]) <= TOL["fp64"] * ref["h2"]
+
+
+def test_grad_fp64(c1_case):
+    w, p, om, spins, lp, e1, e2 = c1_case
+    idx = np.random.default_rng(0).choice(len(spins), 48, replace=False)
+    m = make(w, p)
+    O = m.grad(cuda(spins[idx])).cpu().numpy()
+    ref = oracle.logderiv(om, p, spins[idx])
+    assert max_row_rel_err(O, ref) < TOL["fp64"]
+
+
+@pytest.mark.parametrize("irrep,k", [("A1", 0), ("B1", 0), ("A1", 2), ("B2", 2)])
+def test_stress_fp64(irrep, k, sector16):
+    w = dataclasses.replace(WORKLOADS["4x4_fp64_exact"], irrep=irrep, kx=k, ky=k, n_rbm=2,
+                            n_hidden=8, is_complex=True)
+    p = stress_params(w, 0.3, 5)
+    om = oracle.Model.from_workload(w)
+    _, spins = sector16
+    sp = spins[np.random.default_rng(1).choice(len(spins), 200, replace=False)]
+    keep = nonzero_rows(om, p, sp)
+    sp = sp[keep][:60]
+    m = make(w, p)
+    glp, gel = m.eloc(cuda(sp))
+    assert max_logpsi_err(glp.cpu().numpy(), oracle.logpsi(om, p, sp)) < TOL["fp64"]
+    assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp)) < 1e-9
+    O = m.grad(cuda(sp[:12])).cpu().numpy()
+    assert max_row_rel_err(O, oracle.logderiv(om, p, sp[:12])) < 1e-9
+
+
+# ------------------------------------------------------------------ 6x6 FP32
+
+@pytest.fixture(scope="module")
+def c2_case():
+    w = WORKLOADS["6x6_fp32_eloc"]
+    p = draw_params(w)
+    om = oracle.Model.from_workload(w)
+    spins = random_sz0_spins(w.N, 37, 2002)             # ragged: not a tile multiple
+    return w, p, om, spins
+
+
+def test_logpsi_eloc_fp32(c2_case):
+    w, p, om, spins = c2_case
+    m = make(w, p)
+    glp, gel = m.eloc(cuda(spins))
+    assert max_logpsi_err(glp.cpu().numpy(), oracle.logpsi(om, p, spins)) < TOL["fp32"]
+    assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, spins)) < TOL["fp32"]
+    lp_only = m.logpsi(cuda(spins)).cpu().numpy()
+    assert max_logpsi_err(lp_only, glp.cpu().numpy()) < 1e-12
+
+
+def test_grad_fp32(c2_case):
+    w, p, om, spins = c2_case
+    m = make(w, p)
+    O = m.grad(cuda(spins[:9])).cpu().numpy()
+    assert max_row_rel_err(O, oracle.logderiv(om, p, spins[:9])) < TOL["fp32"]
+
+
+def test_stress_fp32_b1_pi():
+    w = dataclasses.replace(WORKLOADS["6x6_fp32_eloc"], irrep="B1", kx=3, ky=3, n_rbm=2,
+                            n_hidden=16)
+    p = stress_params(w, 0.3, 9)
+    om = oracle.Model.from_workload(w)
+    sp = random_sz0_spins(w.N, 24, 3)
+    sp = sp[nonzero_rows(om, p, sp)][:12]
+    m = make(w, p)
+    glp, gel = m.eloc(cuda(sp))
+    assert max_logpsi_err(glp.cpu().numpy(), oracle.logpsi(om, p, sp)) < TOL["fp32"]
+    assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp)) < 1e-4
+
+
+def test_twohop_fp32():
+    w = WORKLOADS["6x6_fp32_lanczos"]
+    p = stress_params(w, 0.05, 4)
+    om = oracle.Model.from_workload(w)
+    sp = random_sz0_spins(w.N, 2, 11)
+    m = make(w, p)
+    res, e12 = m.lanczos_moments(cuda(sp), exact=False)
+    e12 = e12.cpu().numpy()
+    e1 = oracle.eloc_direct(om, p, sp)
+    e2 = oracle.e2_direct(om, p, sp)
+    assert max_rel_err(e12[:, 0], e1) < TOL["fp32"]
+    assert max_rel_err(e12[:, 1], e2) < TOL["fp32"]
+    ref = oracle.moments(e1, e2)
+    assert abs(res["h1"] - ref["h1"]) < TOL["fp32"] * abs(ref["h1"])
+    assert abs(res["e_p1"] - ref["e_p1"]) < TOL["fp32"] * abs(ref["h1"])
+
+
+def test_twohop_fp32_4x4_exact_mode(sector16):
+    w = dataclasses.replace(WORKLOADS["4x4_fp64_exact"], precision="fp32", is_complex=True,
+                            n_hidden=16)
+    p = stress_params(w, 0.1, 6)
+    om = oracle.Model.from_workload(w)
+    masks, spins = sector16
+    lp = oracle.logpsi(om, p, spins)
+    psi = np.exp(lp - lp.real.max())
+    H = oracle.hamiltonian_sector(om, masks)
+    e1 = (H @ psi) / psi
+    e2 = (H @ (H @ psi)) / psi
+    m = make(w, p)
+    res, e12 = m.lanczos_moments(cuda(spins), exact=True)
+    e12 = e12.cpu().numpy()
+    assert max_rel_err(e12[:, 0], e1) < TOL["fp32"]
+    assert max_rel_err(e12[:, 1], e2) < TOL["fp32"]
+    ref = oracle.moments(e1, e2, weights=np.abs(psi) ** 2)
+    assert abs(res["e_p1"] - ref["e_p1"]) < TOL["fp32"] * abs(ref["h1"])
+    assert abs(res["h2"] - ref["h2"]) < TOL["fp32"] * ref["h2"]
+
+
+# ------------------------------------------------------- split BF16, 8x8, 10x10
+
+@pytest.mark.parametrize("name", ["6x6_fp32_eloc", "8x8_k4_m256", "10x10_m400"])
+@pytest.mark.parametrize("prec", ["bf16x2", "fp32"])
+def test_larger_lattices(name, prec):
+    w = dataclasses.replace(WORKLOADS[name], precision=prec)
+    p = draw_params(w)
+    om = oracle.Model.from_workload(w)
+    sp = random_sz0_spins(w.N, 3, 5)
+    m = make(w, p)
+    glp, gel = m.eloc(cuda(sp))
+    assert max_logpsi_err(glp.cpu().numpy(), oracle.logpsi(om, p, sp)) < TOL[prec]
+    assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp)) < TOL[prec]
+
+
+# ----------------------------------------------------------- sizes and edges
+
+def test_empty_and_single(c2_case):
+    w, p, om, spins = c2_case
+    m = make(w, p)
+    assert m.logpsi(cuda(spins[:0])).numel() == 0
+    lp, el = m.eloc(cuda(spins[:1]))
+    assert max_rel_err(el.cpu().numpy(), oracle.eloc_direct(om, p, spins[:1])) < TOL["fp32"]
+
+
+def test_zero_params_closed_form():
+    w = WORKLOADS["6x6_fp32_eloc"]
+    p = np.zeros((1, w.params_per_rbm), np.complex128)
+    m = make(w, p)
+    sp = random_sz0_spins(w.N, 50, 1)
+    el = m.eloc(cuda(sp), want_logpsi=False).cpu().numpy()
+    assert np.abs(el - w.N * (w.J1 + w.J2) / 2).max() < 1e-5
+
+
+def test_symmetry_invariance_at_full_size():
+    """E_loc(g sigma) = E_loc(sigma) and psi(g sigma) = chi(g) psi(sigma) hold at
+    any size, checked on the 262144-configuration launch."""
+    w = WORKLOADS["6x6_fp32_eloc"]
+    p = draw_params(w)
+    om = oracle.Model.from_workload(w)
+    S = w.n_chains * w.n_per_chain
+    sp = cuda(np.random.default_rng(0).permuted(
+        np.tile(np.r_[np.ones(18, np.int8), -np.ones(18, np.int8)], (S, 1)), axis=1))
+    m = make(w, p)
+    lp, el = m.eloc(sp)
+    h = 8 * 7 + 5
+    perm = torch.from_numpy(om.lat.perms[h]).cuda()
+    lp2, el2 = m.eloc(sp[:, perm])
+    assert max_rel_err(el2.cpu().numpy(), el.cpu().numpy()) < 1e-5
+    assert max_logpsi_err(lp2.cpu().numpy(), lp.cpu().numpy()) < 1e-5
+    rows = np.random.default_rng(1).choice(S, 6, replace=False)
+    spn = sp[rows].cpu().numpy()
+    assert max_rel_err(el.cpu().numpy()[rows], oracle.eloc_direct(om, p, spn)) < TOL["fp32"]
