@@ -213,6 +213,9 @@ nqs_status nqs_create(const nqs_model_desc* d, nqs_ctx** out) {
   c->n_htiles = c->KM / 8;
   c->nk = c->prec == NQS_BF16X2 ? (2 * c->N + 31) / 32 : c->N / 4;
   (void)hipGetDevice(&c->device);
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) !=
+      hipSuccess)
+    c->n_cu = 256;
 
   nqs_status st = NQS_OK;
   st = upload(c, &c->dev.perm, c->geo.perm);

@@ -439,6 +439,8 @@ hipError_t twohop_typed(const nqs_ctx* c, const int8_t* spins, int64_t S, const 
 hipError_t launch_eloc_bonds(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
                              const void* w, double* partial, hipStream_t st) {
   if (S <= 0) return hipSuccess;
+  const hipError_t e = launch_eloc_bonds_reg(c, spins, S, t, w, partial, st);
+  if (e != hipErrorNotSupported) return e;
   return c->prec == NQS_FP64 ? eloc_typed<double>(c, spins, S, t, w, partial, st)
                              : eloc_typed<float>(c, spins, S, t, w, partial, st);
 }

@@ -1,0 +1,205 @@
+// Local energies for models whose tanh(theta) row fits in registers
+// (K*M <= 128 hidden units): persistent workgroups keep the +tanh(D) bond
+// table in LDS for the whole launch and every lane keeps its image's
+// tanh(theta) row in VGPRs, so the exchange product of Sec. 3.2, Eq. (10)
+// reads one LDS word pair per factor and nothing from HBM.
+//
+// Sign folding: with s = +-1 and M even (M is a multiple of 8),
+//   prod_h (1 + s t_h T_h) = prod_h (s + t_h T_h),
+// so the sign enters as the addend of the first FMA and only the +T table
+// is stored (8 VALU operations per factor, as with a pre-signed table).
+//
+// Lane = (image g of a 32-image tile, half of the antiparallel bond list);
+// two bonds per pass and two partial products per bond (even / odd h) give
+// four independent FMA chains per lane.
+#include "device_common.h"
+#include "nqs_internal.h"
+
+namespace nqs {
+
+namespace {
+
+constexpr int kRegWaves = 8;
+
+template <typename R> struct Vec2;
+template <> struct Vec2<float> { using type = float4; };   // two complex floats
+template <> struct Vec2<double> { using type = double2; }; // one complex double
+
+template <typename R, int N, int K, int M>
+struct RegCfg {
+  static constexpr int NB = 4 * N;
+  static constexpr int KM = K * M;
+  // T row stride in R units: 2 KM plus padding that staggers LDS banks
+  static constexpr int STRIDE = 2 * KM + (sizeof(R) == 4 ? 4 : 2);
+  static constexpr size_t LDS = (size_t)NB * STRIDE * sizeof(R) + (size_t)kRegWaves * NB * 2;
+};
+
+__device__ __forceinline__ int build_list(const int8_t* srow, const int32_t* bonds, int NB,
+                                          int16_t* list, int lane) {
+  int n = 0;
+  for (int base = 0; base < NB; base += 64) {
+    const int b = base + lane;
+    bool anti = false;
+    if (b < NB) anti = srow[bonds[2 * b]] != srow[bonds[2 * b + 1]];
+    const unsigned long long m = __ballot(anti);
+    const int pos = __popcll(m & ((1ull << lane) - 1ull));
+    if (anti) list[n + pos] = (int16_t)b;
+    n += __popcll(m);
+  }
+  wave_sync_lds();
+  return n;
+}
+
+// P <- P * (s + t T)
+template <typename R>
+__device__ __forceinline__ void mul_s_plus(R& pr, R& pi, R s, R tr, R ti, R Tr, R Ti) {
+  const R a = fmaf_t(tr, Tr, fmaf_t(-ti, Ti, s));
+  const R b = fmaf_t(tr, Ti, ti * Tr);
+  const R nr = fmaf_t(pr, a, -(pi * b));
+  pi = fmaf_t(pr, b, pi * a);
+  pr = nr;
+}
+
+template <typename R, int N, int K, int M>
+__global__ __launch_bounds__(64 * kRegWaves) void eloc_reg_kernel(
+    const int8_t* __restrict__ spins, int64_t S, int G, int n_htiles,
+    const int32_t* __restrict__ bonds, const int32_t* __restrict__ bmap, const R* __restrict__ t,
+    const R* __restrict__ w, const R* __restrict__ Tpm, const R* __restrict__ F,
+    double* __restrict__ partial) {
+  using Cfg = RegCfg<R, N, K, M>;
+  constexpr int NB = Cfg::NB, KM = Cfg::KM, ST = Cfg::STRIDE;
+  __shared__ __align__(16) R Tl[NB * ST];
+  __shared__ int16_t lists[kRegWaves][NB];
+
+  for (int idx = threadIdx.x; idx < NB * KM; idx += blockDim.x) {
+    const int beta = idx / KM, h = idx % KM;
+    const R* src = Tpm + ((size_t)beta * 2 * KM + h) * 2;   // + sign rows
+    Tl[beta * ST + 2 * h] = src[0];
+    Tl[beta * ST + 2 * h + 1] = src[1];
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ntiles = G / 32;
+  const int64_t n_items = S * ntiles;
+  const int64_t stride = (int64_t)gridDim.x * kRegWaves;
+  int16_t* list = lists[wv];
+  for (int64_t item = (int64_t)blockIdx.x * kRegWaves + wv; item < n_items; item += stride) {
+    const int64_t s = item / ntiles;
+    const int tile = (int)(item % ntiles);
+    const int g = tile * 32 + (lane & 31);
+    const int half = lane >> 5;
+    const int8_t* srow = spins + s * N;
+    const int nc = build_list(srow, bonds, NB, list, lane);
+
+    R tr[KM], ti[KM];
+#pragma unroll
+    for (int ht = 0; ht < KM / 8; ++ht) {
+      const R* tp = t + (((size_t)s * n_htiles + ht) * G + g) * 16;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        tr[8 * ht + e] = tp[2 * e];
+        ti[8 * ht + e] = tp[2 * e + 1];
+      }
+    }
+    R wr[K], wi[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      wr[k] = w[(((size_t)s * K + k) * G + g) * 2];
+      wi[k] = w[(((size_t)s * K + k) * G + g) * 2 + 1];
+    }
+
+    double accr = 0.0, acci = 0.0;
+    for (int i0 = half; i0 < nc; i0 += 4) {
+      int beta[2], sidx[2];
+      R sgn[2], valid[2];
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const int ii = i0 + 2 * n;
+        valid[n] = ii < nc ? R(1) : R(0);
+        const int b = list[ii < nc ? ii : i0];
+        const int v = bmap[(size_t)g * NB + b];
+        beta[n] = v >> 1;
+        const int s_b = -(int)srow[bonds[2 * b]];
+        const int sp = (v & 1) ? -s_b : s_b;
+        sgn[n] = (R)sp;
+        sidx[n] = sp > 0 ? 0 : 1;
+      }
+      const R* T0 = Tl + beta[0] * ST;
+      const R* T1 = Tl + beta[1] * ST;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        R pe0r = 1, pe0i = 0, po0r = 1, po0i = 0, pe1r = 1, pe1i = 0, po1r = 1, po1i = 0;
+#pragma unroll
+        for (int hh = 0; hh < M; hh += 2) {
+          const int h = k * M + hh;
+          if constexpr (sizeof(R) == 4) {
+            const float4 a = *reinterpret_cast<const float4*>(T0 + 2 * h);
+            const float4 c = *reinterpret_cast<const float4*>(T1 + 2 * h);
+            mul_s_plus<R>(pe0r, pe0i, sgn[0], tr[h], ti[h], a.x, a.y);
+            mul_s_plus<R>(po0r, po0i, sgn[0], tr[h + 1], ti[h + 1], a.z, a.w);
+            mul_s_plus<R>(pe1r, pe1i, sgn[1], tr[h], ti[h], c.x, c.y);
+            mul_s_plus<R>(po1r, po1i, sgn[1], tr[h + 1], ti[h + 1], c.z, c.w);
+          } else {
+            const double2 a0 = *reinterpret_cast<const double2*>(T0 + 2 * h);
+            const double2 a1 = *reinterpret_cast<const double2*>(T0 + 2 * h + 2);
+            const double2 c0 = *reinterpret_cast<const double2*>(T1 + 2 * h);
+            const double2 c1 = *reinterpret_cast<const double2*>(T1 + 2 * h + 2);
+            mul_s_plus<R>(pe0r, pe0i, sgn[0], tr[h], ti[h], a0.x, a0.y);
+            mul_s_plus<R>(po0r, po0i, sgn[0], tr[h + 1], ti[h + 1], a1.x, a1.y);
+            mul_s_plus<R>(pe1r, pe1i, sgn[1], tr[h], ti[h], c0.x, c0.y);
+            mul_s_plus<R>(po1r, po1i, sgn[1], tr[h + 1], ti[h + 1], c1.x, c1.y);
+          }
+        }
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          const R per = n ? pe1r : pe0r, pei = n ? pe1i : pe0i;
+          const R por = n ? po1r : po0r, poi = n ? po1i : po0i;
+          const R pr = per * por - pei * poi, pi = per * poi + pei * por;
+          const R* f = F + (((size_t)k * NB + beta[n]) * 2 + sidx[n]) * 2;
+          const R fr = f[0] * wr[k] - f[1] * wi[k], fi = f[0] * wi[k] + f[1] * wr[k];
+          accr += (double)(valid[n] * (fr * pr - fi * pi));
+          acci += (double)(valid[n] * (fr * pi + fi * pr));
+        }
+      }
+    }
+    accr = wave_sum(accr);
+    acci = wave_sum(acci);
+    if (lane == 0) {
+      partial[2 * item] = accr;
+      partial[2 * item + 1] = acci;
+    }
+    wave_sync_lds();   // the list is rewritten for the next item
+  }
+}
+
+template <typename R, int N, int K, int M>
+hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t, const void* w,
+               double* partial, hipStream_t st) {
+  const int64_t items = S * (c->G / 32);
+  int64_t blocks = (items + kRegWaves - 1) / kRegWaves;
+  blocks = std::min<int64_t>(blocks, c->n_cu > 0 ? c->n_cu : 256);
+  eloc_reg_kernel<R, N, K, M><<<(unsigned)blocks, 64 * kRegWaves, 0, st>>>(
+      spins, S, c->G, c->n_htiles, c->dev.bonds, c->dev.bmap, (const R*)t, (const R*)w,
+      (const R*)c->par.Tpm, (const R*)c->par.F, partial);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Returns hipErrorNotSupported when no register-resident variant covers the model.
+hipError_t launch_eloc_bonds_reg(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
+                                 const void* w, double* partial, hipStream_t st) {
+  const int N = c->N, K = c->K, M = c->M;
+  if (c->prec == NQS_FP64) {
+    if (N == 16 && K == 1 && M == 16) return run<double, 16, 1, 16>(c, spins, S, t, w, partial, st);
+    if (N == 16 && K == 2 && M == 8) return run<double, 16, 2, 8>(c, spins, S, t, w, partial, st);
+  } else {
+    if (N == 16 && K == 1 && M == 16) return run<float, 16, 1, 16>(c, spins, S, t, w, partial, st);
+    if (N == 36 && K == 1 && M == 72) return run<float, 36, 1, 72>(c, spins, S, t, w, partial, st);
+    if (N == 36 && K == 2 && M == 16) return run<float, 36, 2, 16>(c, spins, S, t, w, partial, st);
+  }
+  return hipErrorNotSupported;
+}
+
+}  // namespace nqs

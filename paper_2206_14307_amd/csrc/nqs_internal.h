@@ -77,6 +77,7 @@ struct nqs_ctx {
   nqs::ParamTables par;
   std::string last_error;
   int device = 0;
+  int n_cu = 0;                   // compute units of the device (persistent grids)
   nqs::Profiler prof;
 };
 
@@ -115,6 +116,8 @@ hipError_t launch_lse(const nqs_ctx* c, const double* L, int64_t S, double* logp
 // Bond-exchange sums: partial[s][tile] = sum_{b anti} (J_b/2) sum_{g in tile, k} w R.
 hipError_t launch_eloc_bonds(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
                              const void* w, double* partial, hipStream_t st);
+hipError_t launch_eloc_bonds_reg(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
+                                 const void* w, double* partial, hipStream_t st);
 hipError_t launch_eloc_finish(const nqs_ctx* c, const int8_t* spins, int64_t S,
                               const double* partial, double* eloc_out, int eloc_stride,
                               hipStream_t st);
