@@ -51,8 +51,13 @@ ChunkSizes per_sample(const nqs_ctx* c) {
   return z;
 }
 
+// nqs_eloc runs the fused kernel when a register-resident variant covers the model
+bool fused_eloc(const nqs_ctx* c, int op) { return op == NQS_OP_ELOC && eloc_fused_supported(c); }
+size_t fused_part_bytes(const nqs_ctx* c) { return (size_t)(c->G / 16) * 6 * 8; }
+
 size_t chunk_bytes_per_sample(const nqs_ctx* c, int op) {
   const ChunkSizes z = per_sample(c);
+  if (fused_eloc(c, op)) return fused_part_bytes(c) + 16;
   switch (op) {
     case NQS_OP_LOGPSI: return z.L;
     case NQS_OP_ELOC: return z.L + z.w + z.t + z.partial;
@@ -106,6 +111,12 @@ Work plan(const nqs_ctx* c, int op, int64_t S, void* ws) {
   }
   const int64_t ch = chunk_of(c, op, S);
   wk.chunk = ch;
+  if (fused_eloc(c, op)) {
+    wk.partial = (double*)cv.take(fused_part_bytes(c) * ch);
+    wk.lp = (double*)cv.take((size_t)16 * ch);
+    wk.bytes = cv.off;
+    return wk;
+  }
   wk.L = (double*)cv.take(z.L * ch);
   if (op != NQS_OP_LOGPSI) {
     wk.w = cv.take(z.w * ch);
@@ -326,10 +337,15 @@ nqs_status nqs_eloc(nqs_ctx* c, const int8_t* spins, int64_t S, double* logpsi_o
   if (s != NQS_OK) return s;
   if (S > 0 && !eloc_out) return fail(c, NQS_ERR_ARG, "eloc_out is NULL");
   const Work wk = plan(c, NQS_OP_ELOC, S, ws);
+  const bool fused = fused_eloc(c, NQS_OP_ELOC);
   for (int64_t s0 = 0; s0 < S; s0 += wk.chunk) {
     const int64_t n = std::min(wk.chunk, S - s0);
     double* lp = logpsi_out ? logpsi_out + 2 * s0 : wk.lp;
-    const hipError_t e = eloc_chunk(c, wk, spins + s0 * c->N, n, lp, eloc_out + 2 * s0, 2, st);
+    const int8_t* sp = spins + s0 * c->N;
+    const hipError_t e =
+        fused ? NQS_RUN(c, K_ELOC, st,
+                        launch_eloc_fused(c, sp, n, wk.partial, lp, eloc_out + 2 * s0, 2, st))
+              : eloc_chunk(c, wk, sp, n, lp, eloc_out + 2 * s0, 2, st);
     if (e != hipSuccess) return hip_fail(c, e, "eloc launch");
   }
   return NQS_OK;

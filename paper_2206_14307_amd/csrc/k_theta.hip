@@ -16,78 +16,11 @@
 // so sum_h log 2cosh(theta_h) = sum_h |x_h| + log prod_h c_h, with the product
 // kept as (mantissa, binary exponent) -- one log/atan2 per (RBM, image)
 // instead of one per hidden unit.  sum |x| is accumulated in FP64.
-#include "device_common.h"
-#include "nqs_internal.h"
+#include "theta_common.h"
 
 namespace nqs {
 
 namespace {
-
-template <int PREC> struct ThetaTraits;
-template <> struct ThetaTraits<NQS_FP64> {
-  using R = double;
-  using Acc = f64x4;
-  using BFrag = double;
-  using AFrag = double;
-};
-template <> struct ThetaTraits<NQS_FP32> {
-  using R = float;
-  using Acc = f32x4;
-  using BFrag = float;
-  using AFrag = float;
-};
-template <> struct ThetaTraits<NQS_BF16X2> {
-  using R = float;
-  using Acc = f32x4;
-  using BFrag = bf16x8;
-  using AFrag = bf16x8;
-};
-
-template <int N, int PREC> constexpr int nk_of() {
-  return PREC == NQS_BF16X2 ? (2 * N + 31) / 32 : N / 4;
-}
-
-__device__ __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ double exp_t(double v) { return exp(v); }
-__device__ __forceinline__ float exp_t(float v) { return __expf(v); }
-__device__ __forceinline__ void sincos_t(double v, double* s, double* c) { sincos(v, s, c); }
-__device__ __forceinline__ void sincos_t(float v, float* s, float* c) { sincosf(v, s, c); }
-__device__ __forceinline__ double rcp_t(double v) { return 1.0 / v; }
-__device__ __forceinline__ float rcp_t(float v) { return __frcp_rn(v); }
-
-// Build the B-operand fragments of one 16-image column block.
-template <int N, int PREC>
-__device__ __forceinline__ void load_bfrag(const int8_t* srow, const uint8_t* prow, int q,
-                                           typename ThetaTraits<PREC>::BFrag* bx) {
-  constexpr int NK = nk_of<N, PREC>();
-  if constexpr (PREC == NQS_BF16X2) {
-#pragma unroll
-    for (int kk = 0; kk < NK; ++kk) {
-      bf16x8 v;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int kap = 32 * kk + 8 * q + e;
-        float x = 0.f;
-        if (kap < 2 * N) x = 0.5f * (float)srow[prow[kap < N ? kap : kap - N]];
-        v[e] = (__bf16)x;
-      }
-      bx[kk] = v;
-    }
-  } else {
-    using R = typename ThetaTraits<PREC>::R;
-#pragma unroll
-    for (int kk = 0; kk < NK; ++kk) bx[kk] = R(0.5) * (R)srow[prow[4 * kk + q]];
-  }
-}
 
 template <int N, int PREC, int CB>
 __global__ __launch_bounds__(256) void theta_kernel(
@@ -154,23 +87,10 @@ __global__ __launch_bounds__(256) void theta_kernel(
         for (int u = 0; u < 2; ++u) {
           const R x = (R)acc[b][2 * u] + (u ? b1r : b0r);
           const R y = (R)acc[b][2 * u + 1] + (u ? b1i : b0i);
-          const R ax = x < R(0) ? -x : x;
-          const R sg = x < R(0) ? R(-1) : R(1);
-          const R e = exp_t(R(-2) * ax);
-          R sy, cy;
-          sincos_t(y, &sy, &cy);
-          const R cr = (R(1) + e) * cy;
-          const R ci = sg * (R(1) - e) * sy;
-          const R nr = pr[b] * cr - pi[b] * ci;
-          pi[b] = pr[b] * ci + pi[b] * cr;
-          pr[b] = nr;
-          sax[b] += (double)ax;
-          if (t_out) {
-            const R d = fmaf_t(R(2) * e, cy * cy - sy * sy, fmaf_t(e, e, R(1)));
-            const R inv = rcp_t(d);
-            tv[2 * u] = sg * (R(1) - e * e) * inv;
-            tv[2 * u + 1] = R(4) * e * sy * cy * inv;
-          }
+          if (t_out)
+            logcosh_step<R, true>(x, y, pr[b], pi[b], sax[b], tv[2 * u], tv[2 * u + 1]);
+          else
+            logcosh_step<R, false>(x, y, pr[b], pi[b], sax[b], tv[2 * u], tv[2 * u + 1]);
         }
         if (t_out && live[b]) {
           R* dst = t_out + ((((size_t)s_of[b] * n_htiles + ht) * G + g_of[b]) * 8 + 2 * q) * 2;
@@ -180,16 +100,7 @@ __global__ __launch_bounds__(256) void theta_kernel(
       }
       if ((tt & 7) == 7) {
 #pragma unroll
-        for (int b = 0; b < CB; ++b) {
-          const R m = fmax(fabs(pr[b]), fabs(pi[b]));
-          if (m > R(0)) {
-            int ex;
-            frexp(m, &ex);
-            pr[b] = ldexp(pr[b], -ex);
-            pi[b] = ldexp(pi[b], -ex);
-            pe[b] += ex;
-          }
-        }
+        for (int b = 0; b < CB; ++b) renorm(pr[b], pi[b], pe[b]);
       }
     }
     // combine the four lane groups holding different hidden units of one image
