@@ -164,8 +164,12 @@ nqs_status nqs_chain_init(nqs_ctx* ctx, const int8_t* spins, int64_t n_chains,
  * n_skip = 0 selects N_skip = max(1, ceil(5 P / A)) (capped at 1000) from the
  * A accepted out of P burn-in proposals of all chains (Sec. 3.4, N_skip = 5/r).
  * chain_state [n_chains][4] is read and updated; spins_out [n_chains*n_per_chain][N]
- * (chain-major); acc_rate_out [n_chains] float (sampling phase); n_skip_out
- * (device int32, optional) receives the N_skip used. */
+ * (chain-major); acc_rate_out [n_chains] float (sampling phase; NaN for a
+ * chain whose state is not in the Sz = 0 sector, which is left unchanged);
+ * n_skip_out (device int32, optional) receives the N_skip used.  The chain
+ * caches live in the workspace (nqs_workspace_bytes(NQS_OP_SAMPLE, n_chains))
+ * and are rebuilt from the spins every 256 proposals.  Synchronises the
+ * stream once when n_skip = 0 (to size the sampling phase). */
 nqs_status nqs_sample(nqs_ctx* ctx, int64_t n_chains, int64_t n_per_chain, int32_t n_skip,
                       int32_t n_burn, uint64_t seed, uint64_t* chain_state, int8_t* spins_out,
                       float* acc_rate_out, int32_t* n_skip_out, void* ws, size_t ws_bytes,

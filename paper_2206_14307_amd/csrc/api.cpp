@@ -150,7 +150,7 @@ nqs_status upload(nqs_ctx* c, T** dst, const std::vector<T>& src) {
 }
 
 void free_all(nqs_ctx* c) {
-  void* ptrs[] = {c->dev.perm, c->dev.bonds, c->dev.bond_J, c->dev.bmap, c->dev.chi,
+  void* ptrs[] = {c->dev.perm, c->dev.perminv, c->dev.bonds, c->dev.bond_J, c->dev.bmap, c->dev.chi,
                   c->par.params, c->par.wfrag, c->par.bias, c->par.avec, c->par.Tpm,
                   c->par.F, c->par.Tpair, c->par.Fpair, c->par.flag};
   for (void* p : ptrs)
@@ -186,11 +186,7 @@ size_t nqs_workspace_bytes(const nqs_ctx* c, int op, int64_t S) {
     return align_up(Sz * Sz * 16) + align_up(Sz * (size_t)c->P * 8) + 4 * align_up(Sz * 16) +
            align_up((size_t)c->P * 16) + align_up(64 * 16);
   }
-  if (op == NQS_OP_SAMPLE) {
-    const size_t n = (size_t)S;
-    return align_up(n * (size_t)c->G * c->KM * 2 * real_size(c)) +
-           align_up(n * (size_t)c->K * c->G * 2 * real_size(c)) + align_up(n * 32) + align_up(64);
-  }
+  if (op == NQS_OP_SAMPLE) return sample_workspace_bytes(c, S);
   return plan(c, op, S, nullptr).bytes;
 }
 
@@ -230,6 +226,10 @@ nqs_status nqs_create(const nqs_model_desc* d, nqs_ctx** out) {
 
   nqs_status st = NQS_OK;
   st = upload(c, &c->dev.perm, c->geo.perm);
+  std::vector<uint8_t> inv(c->geo.perm.size());
+  for (int g = 0; g < c->G; ++g)
+    for (int l = 0; l < c->N; ++l) inv[(size_t)g * c->N + c->geo.perm[(size_t)g * c->N + l]] = l;
+  if (st == NQS_OK) st = upload(c, &c->dev.perminv, inv);
   std::vector<int32_t> bonds(2 * c->NB);
   for (int b = 0; b < c->NB; ++b) {
     bonds[2 * b] = c->geo.bond_i[b];
@@ -250,6 +250,8 @@ nqs_status nqs_create(const nqs_model_desc* d, nqs_ctx** out) {
                 {&c->par.avec, (size_t)c->K * c->N * 2 * rs},
                 {&c->par.Tpm, (size_t)c->NB * 2 * c->KM * 2 * rs},
                 {&c->par.F, (size_t)c->K * c->NB * 2 * 2 * rs},
+                {&c->par.Tpair, (size_t)c->N * c->N * c->KM * 2 * rs},
+                {&c->par.Fpair, (size_t)c->K * c->N * c->N * 2 * rs},
                 {(void**)&c->par.flag, 16}};
   for (auto& a : allocs) {
     if (st != NQS_OK) break;

@@ -157,6 +157,62 @@ __global__ void prep_F_kernel(const double2* p, int Prbm, int K, int M, int N, i
   }
 }
 
+// Site-pair tables of the sampler's exchange move (up site at image position
+// p, down site at q, so theta -> theta - (W_p - W_q)):
+// Tpair[p][q][h] = tanh(W_hp - W_hq), Fpair[k][p][q] = exp(-(a_p - a_q)) prod_h cosh(W_hp - W_hq).
+template <typename R>
+__global__ void prep_Tpair_kernel(const double2* p, int Prbm, int M, int N, int KM, R* Tpair) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)N * N * KM) return;
+  const int h = idx % KM;
+  const int pq = idx / KM;
+  const int sp = pq / N, sq = pq % N;
+  const double2 wp = Wval(p, Prbm, M, N, h, sp);
+  const double2 wq = Wval(p, Prbm, M, N, h, sq);
+  const double2 t = ctanh64(wp.x - wq.x, wp.y - wq.y);
+  Tpair[2 * idx] = (R)t.x;
+  Tpair[2 * idx + 1] = (R)t.y;
+}
+
+template <typename R>
+__global__ void prep_Fpair_kernel(const double2* p, int Prbm, int K, int M, int N, int use_bias,
+                                  R* Fpair) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= K * N * N) return;
+  const int k = idx / (N * N), sp = (idx / N) % N, sq = idx % N;
+  double cr = 1.0, ci = 0.0;
+  for (int hh = 0; hh < M; ++hh) {
+    const double2 wp = Wval(p, Prbm, M, N, k * M + hh, sp);
+    const double2 wq = Wval(p, Prbm, M, N, k * M + hh, sq);
+    const double2 c = ccosh64(wp.x - wq.x, wp.y - wq.y);
+    const double nr = cr * c.x - ci * c.y;
+    ci = cr * c.y + ci * c.x;
+    cr = nr;
+  }
+  double ar = 0.0, ai = 0.0;
+  if (use_bias) {
+    const double2 ap = p[(size_t)k * Prbm + (size_t)M * N + sp];
+    const double2 aq = p[(size_t)k * Prbm + (size_t)M * N + sq];
+    ar = ap.x - aq.x;
+    ai = ap.y - aq.y;
+  }
+  const double2 e = cexp64(-ar, -ai);
+  Fpair[2 * idx] = (R)(e.x * cr - e.y * ci);
+  Fpair[2 * idx + 1] = (R)(e.x * ci + e.y * cr);
+}
+
+template <typename R>
+hipError_t prep_pairs_typed(const nqs_ctx* c, hipStream_t st) {
+  const double2* p = reinterpret_cast<const double2*>(c->par.params);
+  const int64_t nT = (int64_t)c->N * c->N * c->KM;
+  prep_Tpair_kernel<R><<<(unsigned)((nT + 255) / 256), 256, 0, st>>>(p, c->P_rbm, c->M, c->N,
+                                                                       c->KM, (R*)c->par.Tpair);
+  const int nF = c->K * c->N * c->N;
+  prep_Fpair_kernel<R><<<(nF + 63) / 64, 64, 0, st>>>(p, c->P_rbm, c->K, c->M, c->N,
+                                                      c->d.use_bias, (R*)c->par.Fpair);
+  return hipGetLastError();
+}
+
 __global__ void check_finite_kernel(const double* p, int64_t n, double* flag) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -194,7 +250,13 @@ hipError_t launch_check_finite(const double* p, int64_t n, double* flag, hipStre
 }
 
 hipError_t launch_prep(const nqs_ctx* c, hipStream_t st) {
-  return c->prec == NQS_FP64 ? prep_typed<double>(c, st) : prep_typed<float>(c, st);
+  hipError_t e = c->prec == NQS_FP64 ? prep_typed<double>(c, st) : prep_typed<float>(c, st);
+  if (e != hipSuccess) return e;
+  return launch_prep_pairs(c, st);
+}
+
+hipError_t launch_prep_pairs(const nqs_ctx* c, hipStream_t st) {
+  return c->prec == NQS_FP64 ? prep_pairs_typed<double>(c, st) : prep_pairs_typed<float>(c, st);
 }
 
 }  // namespace nqs

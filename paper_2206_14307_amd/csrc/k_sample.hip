@@ -1,23 +1,390 @@
-// Exchange Metropolis sampler (placeholder until the sampling kernels land).
+// Exchange Metropolis sampling of |psi|^2 (Sec. 3.2; N_skip rule of Sec. 3.4).
+//
+// One workgroup per chain, one lane per symmetry image.  The chain keeps, in
+// the caller's workspace, tanh(theta) of every (image, hidden unit) and the
+// normalised image weights u_kg = chi_g psi_s^(k)(g sigma)/psi(sigma), in the
+// layouts the theta and log-sum-exp kernels write (those kernels build the
+// cache and refresh it between launches, which bounds rounding drift).
+//
+// A proposal exchanges the up site i and the down site j.  In image g they
+// sit at p = perm_g^-1(i), q = perm_g^-1(j), so theta -> theta - (W_p - W_q)
+// and, with T = tanh(W_p - W_q) (the precomputed site-pair table),
+//   psi_s(g sigma')/psi_s(g sigma) = exp(-(a_p - a_q)) prod_h cosh(W_hp - W_hq)
+//                                    * prod_h (t_h T_h - 1)        (M even),
+// the ratio is psi(sigma')/psi(sigma) = sum_kg u_kg R_kg, and an accepted
+// move updates t' = (t - T)/(1 - t T) (tanh addition) and u' = u R / ratio.
+//
+// Randomness: proposal n of a chain uses Philox4x64-10 (Salmon et al., SC'11)
+// with counter (n, 0, 0, 0) and key (seed, chain id): r0 picks the
+// k-th up site, k = (r0 >> 11) * (N/2) >> 53, r1 the k'-th down site, and the
+// move is accepted iff (r2 >> 11) * 2^-53 < |ratio|^2.
+#include <algorithm>
+#include <string>
+
+#include "device_common.h"
 #include "nqs_internal.h"
+
+namespace nqs {
+
+namespace {
+
+constexpr int kSegment = 256;      // proposals per launch between cache refreshes
+constexpr int kNskipMax = 1000;
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                              uint64_t k0, uint64_t k1, uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// position of the k-th (0-based) set bit of a 64-bit word (k < popcount)
+__device__ __forceinline__ int select64(uint64_t x, int k) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const uint64_t low = x & ((1ull << w) - 1ull);
+    const int c = __popcll(low);
+    if (k >= c) {
+      k -= c;
+      x >>= w;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+__device__ __forceinline__ int select128(uint64_t lo, uint64_t hi, int k) {
+  const int c = __popcll(lo);
+  return k < c ? select64(lo, k) : 64 + select64(hi, k - c);
+}
+
+template <typename R>
+__global__ __launch_bounds__(1024) void sample_kernel(
+    int N, int G, int K, int M, int n_htiles, const uint8_t* __restrict__ perminv,
+    const R* __restrict__ Tpair, const R* __restrict__ Fpair, R* __restrict__ t, R* __restrict__ w,
+    uint64_t* __restrict__ state, int n_prop, int phase, int64_t p0, const int32_t* nskip_dev,
+    int n_skip_host, uint64_t seed, int8_t* __restrict__ spins_out, int64_t n_per_chain,
+    int64_t* __restrict__ acc_out, int8_t* __restrict__ cur_spins) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* Rg = reinterpret_cast<R*>(smem);                                  // [G][K] complex
+  double* red = reinterpret_cast<double*>(smem + (size_t)G * K * 2 * sizeof(R));  // [2][16]
+  const int64_t c = blockIdx.x;
+  const int g = threadIdx.x, lane = g & 63, wv = g >> 6, nw = (blockDim.x + 63) >> 6;
+  const bool active = g < G;
+  uint64_t lo = state[4 * c], hi = state[4 * c + 1], ctr = state[4 * c + 2];
+  const uint64_t id = state[4 * c + 3];
+  const uint64_t nmask_lo = N >= 64 ? ~0ull : ((1ull << N) - 1ull);
+  const uint64_t nmask_hi = N > 64 ? ((1ull << (N - 64)) - 1ull) : 0ull;
+  const int half = N / 2;
+  const bool valid = (__popcll(lo & nmask_lo) + __popcll(hi & nmask_hi) == half) &&
+                     ((lo & ~nmask_lo) == 0) && ((hi & ~nmask_hi) == 0);
+  const int n_skip = phase == 1 ? (nskip_dev ? *nskip_dev : n_skip_host) : 1;
+  const int KM = K * M;
+  R* tc = t + (size_t)c * n_htiles * G * 16;
+  R* wc = w + (size_t)c * K * G * 2;
+  int64_t acc = 0;
+  for (int r = 0; r < n_prop && valid; ++r) {
+    uint64_t rnd[4];
+    philox4x64_10(ctr, 0, 0, 0, seed, id, rnd);
+    const int kup = (int)(((rnd[0] >> 11) * (uint64_t)half) >> 53);
+    const int kdn = (int)(((rnd[1] >> 11) * (uint64_t)half) >> 53);
+    const int i = select128(lo, hi, kup);
+    const int j = select128(~lo & nmask_lo, ~hi & nmask_hi, kdn);
+    double cr = 0.0, ci = 0.0;
+    int l1 = 0, l2 = 0;
+    if (active) {
+      l1 = perminv[(size_t)g * N + i];
+      l2 = perminv[(size_t)g * N + j];
+      const R* Trow = Tpair + ((size_t)l1 * N + l2) * KM * 2;
+      for (int k = 0; k < K; ++k) {
+        R pr = 1, pi = 0;
+        for (int h8 = k * M; h8 < (k + 1) * M; h8 += 8) {
+          const R* tp = tc + ((size_t)(h8 >> 3) * G + g) * 16;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const R tr = tp[2 * e], ti = tp[2 * e + 1];
+            const R Tr = Trow[2 * (h8 + e)], Ti = Trow[2 * (h8 + e) + 1];
+            const R a = fmaf_t(tr, Tr, fmaf_t(-ti, Ti, R(-1)));
+            const R b = fmaf_t(tr, Ti, ti * Tr);
+            const R nr = fmaf_t(pr, a, -(pi * b));
+            pi = fmaf_t(pr, b, pi * a);
+            pr = nr;
+          }
+        }
+        const R* f = Fpair + (((size_t)k * N + l1) * N + l2) * 2;
+        const R rr = f[0] * pr - f[1] * pi, ri = f[0] * pi + f[1] * pr;
+        Rg[2 * (g * K + k)] = rr;
+        Rg[2 * (g * K + k) + 1] = ri;
+        const R wr = wc[2 * (k * G + g)], wi = wc[2 * (k * G + g) + 1];
+        cr += (double)(wr * rr - wi * ri);
+        ci += (double)(wr * ri + wi * rr);
+      }
+    }
+    cr = wave_sum(cr);
+    ci = wave_sum(ci);
+    if (lane == 0) {
+      red[wv] = cr;
+      red[16 + wv] = ci;
+    }
+    __syncthreads();
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < nw; ++q) {
+      sr += red[q];
+      si += red[16 + q];
+    }
+    __syncthreads();
+    const double u = (double)(rnd[2] >> 11) * (1.0 / 9007199254740992.0);
+    const bool accept = u < sr * sr + si * si;
+    if (accept) {
+      ++acc;
+      if (active) {
+        const R* Trow = Tpair + ((size_t)l1 * N + l2) * KM * 2;
+        for (int h8 = 0; h8 < KM; h8 += 8) {
+          R* tp = tc + ((size_t)(h8 >> 3) * G + g) * 16;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const R tr = tp[2 * e], ti = tp[2 * e + 1];
+            const R Tr = Trow[2 * (h8 + e)], Ti = Trow[2 * (h8 + e) + 1];
+            // (t - T) / (1 - t T)
+            const R nr = tr - Tr, ni = ti - Ti;
+            const R dr = R(1) - (tr * Tr - ti * Ti), di = -(tr * Ti + ti * Tr);
+            const R inv = R(1) / (dr * dr + di * di);
+            tp[2 * e] = (nr * dr + ni * di) * inv;
+            tp[2 * e + 1] = (ni * dr - nr * di) * inv;
+          }
+        }
+        const double den = sr * sr + si * si;
+        for (int k = 0; k < K; ++k) {
+          const R wr = wc[2 * (k * G + g)], wi = wc[2 * (k * G + g) + 1];
+          const R rr = Rg[2 * (g * K + k)], ri = Rg[2 * (g * K + k) + 1];
+          const double qr = (double)(wr * rr - wi * ri), qi = (double)(wr * ri + wi * rr);
+          wc[2 * (k * G + g)] = (R)((qr * sr + qi * si) / den);
+          wc[2 * (k * G + g) + 1] = (R)((qi * sr - qr * si) / den);
+        }
+      }
+      const int b0 = i < 64 ? i : i - 64, b1 = j < 64 ? j : j - 64;
+      if (i < 64) lo ^= 1ull << b0; else hi ^= 1ull << b0;
+      if (j < 64) lo ^= 1ull << b1; else hi ^= 1ull << b1;
+    }
+    ++ctr;
+    if (phase == 1) {
+      const int64_t idx = p0 + r + 1;
+      if (idx % n_skip == 0) {
+        const int64_t m = idx / n_skip - 1;
+        if (m < n_per_chain && g < N) {
+          const uint64_t bit = g < 64 ? (lo >> g) & 1ull : (hi >> (g - 64)) & 1ull;
+          spins_out[((size_t)c * n_per_chain + m) * N + g] = bit ? 1 : -1;
+        }
+      }
+    }
+  }
+  if (g == 0) {
+    state[4 * c] = lo;
+    state[4 * c + 1] = hi;
+    state[4 * c + 2] = ctr;
+    acc_out[c] += valid ? acc : -(int64_t)1 << 40;
+  }
+  if (g < N) {
+    const uint64_t bit = g < 64 ? (lo >> g) & 1ull : (hi >> (g - 64)) & 1ull;
+    cur_spins[(size_t)c * N + g] = bit ? 1 : -1;
+  }
+}
+
+__global__ void pack_kernel(const int8_t* __restrict__ spins, int64_t n, int N, uint64_t first,
+                            uint64_t* __restrict__ state) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  uint64_t lo = 0, hi = 0;
+  for (int i = 0; i < N; ++i)
+    if (spins[c * N + i] > 0) {
+      if (i < 64) lo |= 1ull << i;
+      else hi |= 1ull << (i - 64);
+    }
+  state[4 * c] = lo;
+  state[4 * c + 1] = hi;
+  state[4 * c + 2] = 0;
+  state[4 * c + 3] = first + (uint64_t)c;
+}
+
+__global__ void unpack_kernel(const uint64_t* __restrict__ state, int64_t n, int N,
+                              int8_t* __restrict__ spins) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * N) return;
+  const int64_t c = idx / N;
+  const int i = (int)(idx % N);
+  const uint64_t word = i < 64 ? state[4 * c] : state[4 * c + 1];
+  spins[idx] = ((word >> (i & 63)) & 1ull) ? 1 : -1;
+}
+
+// N_skip = max(1, ceil(5 P / A)) from the burn-in counts of every chain.
+__global__ void nskip_kernel(const int64_t* __restrict__ acc, int64_t n, int64_t proposals,
+                             int32_t* __restrict__ out) {
+  __shared__ long long part[256];
+  long long a = 0;
+  for (int64_t c = threadIdx.x; c < n; c += 256) a += acc[c] > 0 ? acc[c] : 0;
+  part[threadIdx.x] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long A = 0;
+    for (int q = 0; q < 256; ++q) A += part[q];
+    const long long P = proposals * n;
+    long long ns = A > 0 ? (5 * P + A - 1) / A : kNskipMax;
+    ns = ns < 1 ? 1 : (ns > kNskipMax ? kNskipMax : ns);
+    out[0] = (int32_t)ns;
+  }
+}
+
+__global__ void acc_rate_kernel(const int64_t* __restrict__ acc, int64_t n, int64_t proposals,
+                                float* __restrict__ rate) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  rate[c] = acc[c] < 0 ? NAN : (proposals > 0 ? (float)((double)acc[c] / (double)proposals) : 0.f);
+}
+
+inline size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+}  // namespace
+
+size_t sample_workspace_bytes(const nqs_ctx* c, int64_t C) {
+  const size_t rs = c->prec == NQS_FP64 ? 8 : 4, n = (size_t)std::max<int64_t>(C, 1);
+  return al(n * c->G * c->KM * 2 * rs) + al(n * c->K * c->G * 2 * rs) + al(n * c->K * c->G * 16) +
+         al(n * 16) + al(n * c->N) + 2 * al(n * 8) + al(64);
+}
+
+}  // namespace nqs
+
+using namespace nqs;
 
 extern "C" {
 
 nqs_status nqs_chain_init(nqs_ctx* c, const int8_t* spins, int64_t n_chains,
                           uint64_t first_chain_id, uint64_t* chain_state, hipStream_t st) {
-  (void)spins; (void)n_chains; (void)first_chain_id; (void)chain_state; (void)st;
-  if (c) c->last_error = "nqs_chain_init is not available in this build";
-  return NQS_ERR_ARG;
+  if (!c) return NQS_ERR_ARG;
+  if (n_chains < 0 || (n_chains > 0 && (!spins || !chain_state))) {
+    c->last_error = "chain_init: bad arguments";
+    return NQS_ERR_ARG;
+  }
+  if (n_chains == 0) return NQS_OK;
+  pack_kernel<<<(unsigned)((n_chains + 255) / 256), 256, 0, st>>>(spins, n_chains, c->N,
+                                                                   first_chain_id, chain_state);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    c->last_error = std::string("chain_init: ") + hipGetErrorString(e);
+    return NQS_ERR_DEVICE;
+  }
+  return NQS_OK;
 }
 
 nqs_status nqs_sample(nqs_ctx* c, int64_t n_chains, int64_t n_per_chain, int32_t n_skip,
                       int32_t n_burn, uint64_t seed, uint64_t* chain_state, int8_t* spins_out,
                       float* acc_rate_out, int32_t* n_skip_out, void* ws, size_t ws_bytes,
                       hipStream_t st) {
-  (void)n_chains; (void)n_per_chain; (void)n_skip; (void)n_burn; (void)seed; (void)chain_state;
-  (void)spins_out; (void)acc_rate_out; (void)n_skip_out; (void)ws; (void)ws_bytes; (void)st;
-  if (c) c->last_error = "nqs_sample is not available in this build";
-  return NQS_ERR_ARG;
+  if (!c) return NQS_ERR_ARG;
+  auto fail = [&](nqs_status s, const std::string& m) {
+    c->last_error = m;
+    return s;
+  };
+  if (n_chains < 1 || n_per_chain < 0 || n_skip < 0 || n_burn < 0 || !chain_state)
+    return fail(NQS_ERR_ARG, "sample: bad counts or NULL chain_state");
+  if (n_skip == 0 && n_burn == 0)
+    return fail(NQS_ERR_ARG, "sample: automatic N_skip needs burn-in proposals");
+  if (n_per_chain > 0 && !spins_out) return fail(NQS_ERR_ARG, "sample: spins_out is NULL");
+  if (n_skip > kNskipMax) return fail(NQS_ERR_ARG, "sample: n_skip above 1000");
+  if (c->G > 1024) return fail(NQS_ERR_ARG, "sample: more than 1024 images");
+  const size_t need = sample_workspace_bytes(c, n_chains);
+  if (!ws || ws_bytes < need)
+    return fail(NQS_ERR_ARG, "sample: workspace too small: need " + std::to_string(need));
+  const size_t rs = c->prec == NQS_FP64 ? 8 : 4, n = (size_t)n_chains;
+  char* p = (char*)ws;
+  void* t = p;
+  p += al(n * c->G * c->KM * 2 * rs);
+  void* w = p;
+  p += al(n * c->K * c->G * 2 * rs);
+  double* L = (double*)p;
+  p += al(n * c->K * c->G * 16);
+  double* lp = (double*)p;
+  p += al(n * 16);
+  int8_t* cur = (int8_t*)p;
+  p += al(n * c->N);
+  int64_t* acc_burn = (int64_t*)p;
+  p += al(n * 8);
+  int64_t* acc_samp = (int64_t*)p;
+  p += al(n * 8);
+  int32_t* nsk = (int32_t*)p;
+
+  hipError_t e = hipMemsetAsync(acc_burn, 0, n * 8, st);
+  if (e == hipSuccess) e = hipMemsetAsync(acc_samp, 0, n * 8, st);
+  if (e == hipSuccess) {
+    unpack_kernel<<<(unsigned)((n * c->N + 255) / 256), 256, 0, st>>>(chain_state, n_chains, c->N,
+                                                                       cur);
+    e = hipGetLastError();
+  }
+  const int threads = std::max(64, (c->G + 63) / 64 * 64);
+  const size_t lds = (size_t)c->G * c->K * 2 * rs + 32 * sizeof(double);
+  auto refresh = [&]() -> hipError_t {
+    hipError_t r = launch_theta(c, cur, n_chains, L, t, st);
+    if (r == hipSuccess) r = launch_lse(c, L, n_chains, lp, w, st);
+    return r;
+  };
+  auto run = [&](int phase, int64_t total, int ns_host, const int32_t* ns_dev,
+                 int64_t* acc) -> hipError_t {
+    for (int64_t p0 = 0; p0 < total; p0 += kSegment) {
+      const int cnt = (int)std::min<int64_t>(kSegment, total - p0);
+      hipError_t r = refresh();
+      if (r != hipSuccess) return r;
+      prof_begin(c, K_SAMPLE, st);
+      if (c->prec == NQS_FP64)
+        sample_kernel<double><<<(unsigned)n, threads, lds, st>>>(
+            c->N, c->G, c->K, c->M, c->n_htiles, c->dev.perminv, (const double*)c->par.Tpair,
+            (const double*)c->par.Fpair, (double*)t, (double*)w, chain_state, cnt, phase, p0,
+            ns_dev, ns_host, seed, spins_out, n_per_chain, acc, cur);
+      else
+        sample_kernel<float><<<(unsigned)n, threads, lds, st>>>(
+            c->N, c->G, c->K, c->M, c->n_htiles, c->dev.perminv, (const float*)c->par.Tpair,
+            (const float*)c->par.Fpair, (float*)t, (float*)w, chain_state, cnt, phase, p0,
+            ns_dev, ns_host, seed, spins_out, n_per_chain, acc, cur);
+      prof_end(c, K_SAMPLE, st);
+      r = hipGetLastError();
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  };
+  if (e == hipSuccess) e = run(0, n_burn, 1, nullptr, acc_burn);
+  int ns = n_skip;
+  if (e == hipSuccess && n_skip == 0) {
+    nskip_kernel<<<1, 256, 0, st>>>(acc_burn, n_chains, n_burn, nsk);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&ns, nsk, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  const int64_t total = n_per_chain * (int64_t)ns;
+  if (e == hipSuccess) e = run(1, total, ns, nullptr, acc_samp);
+  if (e == hipSuccess && acc_rate_out) {
+    acc_rate_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(acc_samp, n_chains, total,
+                                                                 acc_rate_out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && n_skip_out) e = hipMemsetD32Async(n_skip_out, ns, 1, st);
+  if (e != hipSuccess) return fail(NQS_ERR_DEVICE, std::string("sample: ") + hipGetErrorString(e));
+  return NQS_OK;
 }
 
 }  // extern "C"

@@ -32,6 +32,7 @@ bool build_geometry(int L, double J1, double J2, int kx, int ky, int irrep, Geom
 // Device-side tables owned by the context.
 struct DeviceTables {
   uint8_t* perm = nullptr;        // [G][N]
+  uint8_t* perminv = nullptr;     // [G][N]  position l with perm_g(l) = site
   int32_t* bonds = nullptr;       // [NB][2]
   double* bond_J = nullptr;       // [NB]
   int32_t* bmap = nullptr;        // [G][NB]
@@ -48,7 +49,7 @@ struct ParamTables {
   void* Tpm = nullptr;            // [NB][2][K*M] complex R: +tanh(D), -tanh(D)
   void* F = nullptr;              // [K][NB][2] complex R: (J/2) exp(s A) prod_h cosh D
   void* Tpair = nullptr;          // [N][N][K*M] complex R: tanh(W_h,p - W_h,q) (sampler)
-  void* Fpair = nullptr;          // [K][N][N] complex R: exp(a_p - a_q) prod_h cosh(...)
+  void* Fpair = nullptr;          // [K][N][N] complex R: exp(-(a_p - a_q)) prod_h cosh(W_h,p - W_h,q)
   double* flag = nullptr;         // [1] non-finite detector
 };
 
@@ -102,6 +103,7 @@ namespace nqs {
 // ----------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return hipGetLastError().
 hipError_t launch_prep(const nqs_ctx* c, hipStream_t st);
+hipError_t launch_prep_pairs(const nqs_ctx* c, hipStream_t st);
 hipError_t launch_check_finite(const double* p, int64_t n, double* flag, hipStream_t st);
 
 // theta = W x + b for every (sample, image), epilogue: per-(k, image)
@@ -133,6 +135,7 @@ hipError_t launch_twohop_finish(const nqs_ctx* c, const int8_t* spins, int64_t S
                                 const double* partial2, double* e1e2, hipStream_t st);
 hipError_t launch_moments(const double* e1e2, const double* logpsi, int64_t S, int exact,
                           double* partial, int nblocks, double* result, hipStream_t st);
+size_t sample_workspace_bytes(const nqs_ctx* c, int64_t n_chains);
 hipError_t launch_grad(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
                        const void* w, void* O_out, hipStream_t st);
 

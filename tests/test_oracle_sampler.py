@@ -68,8 +68,10 @@ def test_sampler_reproduces_exact_distribution():
     sd = O.diag_energy(m, samples)
     obs = np.array([np.isclose(sd, v).sum() for v in vals])
     keep = exp_p * len(samples) >= 5
-    f_exp = np.append(exp_p[keep], exp_p[~keep].sum()) * len(samples)
-    f_obs = np.append(obs[keep], obs[~keep].sum())
+    f_exp, f_obs = exp_p[keep] * len(samples), obs[keep]
+    if (~keep).any():                                   # pool the rare bins
+        f_exp = np.append(f_exp, exp_p[~keep].sum() * len(samples))
+        f_obs = np.append(f_obs, obs[~keep].sum())
     # samples are correlated (N_skip = 4): use a conservative threshold
     chi2 = ((f_obs - f_exp) ** 2 / f_exp).sum()
     assert chi2 < stats.chi2.ppf(0.9999, len(f_obs) - 1) * 3
