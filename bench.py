@@ -213,12 +213,29 @@ def main():
     params = draw_params(w)
     spins_np = random_sz0_spins_fast(w.N, S, 2002)
     # the CPU baseline runs first, in worker processes forked before any GPU use
+    # (on uniformly random Sz = 0 configurations: at these near-uniform amplitudes
+    # they follow the distribution the sampler produces)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, params, spins_np)
     if cpu:
         log(f"cpu baseline done: {cpu['value']:.3g} {cpu['unit']} on {cpu['cores']} cores")
     m = NQS.from_workload(w)
     m.set_params(torch.from_numpy(params.reshape(-1)))
-    sp = torch.from_numpy(spins_np).cuda()
+    # the benchmark's configurations come from the sampler: n_chains x n_per_chain
+    # samples, automatic N_skip, burn-in 20 N proposals per chain
+    init = torch.from_numpy(spins_np[: w.n_chains]).cuda()
+    state = m.chain_init(init)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sp, acc_rate, nskip = m.sample(state, w.n_per_chain, n_skip=0, n_burn=20 * w.N, seed=2002)
+    torch.cuda.synchronize()
+    t_sample = time.perf_counter() - t0
+    nskip = int(nskip.item())
+    sample_leg = {"chains": w.n_chains, "per_chain": w.n_per_chain, "burn_in": 20 * w.N,
+                  "n_skip": nskip, "acceptance": float(acc_rate.mean().item()),
+                  "seconds": t_sample,
+                  "proposals_per_s": w.n_chains * (20 * w.N + w.n_per_chain * nskip) / t_sample}
+    log(f"sampled {S} configurations in {t_sample:.2f} s (N_skip {nskip})")
+    spins_np = sp.cpu().numpy()
     lp = torch.empty(S, dtype=torch.complex128, device="cuda")
     el = torch.empty(S, dtype=torch.complex128, device="cuda")
     ws = m.workspace("eloc", S)
@@ -273,11 +290,11 @@ def main():
         "config": {"workload": args.workload, "lattice": f"{w.L}x{w.L}", "J2": w.J2,
                    "n_rbm": w.n_rbm, "n_hidden": w.n_hidden, "sym_images": w.G,
                    "configs": S, "params": "N(0,0.01) complex, seed %d" % w.seed,
-                   "spins": "uniform random Sz=0 configurations, seed 2002"},
+                   "spins": "exchange Metropolis samples (nqs_sample), seed 2002"},
         "roofline": roofline,
         "errors": errs,
     }
-    legs = {}
+    legs = {"sample": sample_leg}
     if not args.no_legs:
         legs["grad"] = leg_grad(m, sp, S, w.G, w.n_rbm)
         log(f"grad leg: {legs['grad']['ms']:.2f} ms")

@@ -180,12 +180,7 @@ int64_t nqs_num_params(const nqs_ctx* c) { return c ? c->P : -1; }
 
 size_t nqs_workspace_bytes(const nqs_ctx* c, int op, int64_t S) {
   if (!c || S < 0) return 0;
-  if (op == NQS_OP_SR) {
-    // T (S x S complex double), O_bar (S x P complex float), eps, x, column means
-    const size_t Sz = (size_t)S;
-    return align_up(Sz * Sz * 16) + align_up(Sz * (size_t)c->P * 8) + 4 * align_up(Sz * 16) +
-           align_up((size_t)c->P * 16) + align_up(64 * 16);
-  }
+  if (op == NQS_OP_SR) return sr_workspace_bytes(c, S);
   if (op == NQS_OP_SAMPLE) return sample_workspace_bytes(c, S);
   return plan(c, op, S, nullptr).bytes;
 }

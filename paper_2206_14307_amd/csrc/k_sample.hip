@@ -200,7 +200,7 @@ __global__ __launch_bounds__(1024) void sample_kernel(
     state[4 * c] = lo;
     state[4 * c + 1] = hi;
     state[4 * c + 2] = ctr;
-    acc_out[c] += valid ? acc : -(int64_t)1 << 40;
+    acc_out[c] += valid ? acc : -((int64_t)1 << 40);   // marks a chain outside Sz = 0
   }
   if (g < N) {
     const uint64_t bit = g < 64 ? (lo >> g) & 1ull : (hi >> (g - 64)) & 1ull;

@@ -136,6 +136,7 @@ hipError_t launch_twohop_finish(const nqs_ctx* c, const int8_t* spins, int64_t S
 hipError_t launch_moments(const double* e1e2, const double* logpsi, int64_t S, int exact,
                           double* partial, int nblocks, double* result, hipStream_t st);
 size_t sample_workspace_bytes(const nqs_ctx* c, int64_t n_chains);
+size_t sr_workspace_bytes(const nqs_ctx* c, int64_t S);
 hipError_t launch_grad(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
                        const void* w, void* O_out, hipStream_t st);
 
