@@ -57,6 +57,23 @@ def n_antiparallel(spins, bonds):
     return (spins[:, bonds[:, 0]] != spins[:, bonds[:, 1]]).sum(axis=1)
 
 
+def counted_traffic(path=os.path.join(ROOT, "profiles", "eloc_fused_6x6_m72_hbm_counters.json")):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (copy-calibrated), or None when the kernel's
+    sources have changed since the counters were taken."""
+    import hashlib
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in d["kernel_sources"]:
+        h.update(open(os.path.join(ROOT, "paper_2206_14307_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != d["kernel_source_sha256_16"]:
+        return None
+    return d["traffic_bytes_per_launch"]
+
+
 # ------------------------------------------------------------- CPU baseline
 
 def _oracle_chunk(args):
@@ -188,6 +205,29 @@ def leg_precision(name, steps=2):
     return out
 
 
+def leg_sr(name="10x10_m400", S=8192, steps=1):
+    """logpsi + E_loc + O_k for S configurations, then the sample-space SR step."""
+    import torch
+    from paper_2206_14307_amd import NQS
+    from workloads import WORKLOADS, draw_params, random_sz0_spins_fast
+    w = WORKLOADS[name]
+    m = NQS.from_workload(w)
+    p = draw_params(w)
+    m.set_params(torch.from_numpy(p.reshape(-1)))
+    sp = torch.from_numpy(random_sz0_spins_fast(w.N, S, 5005)).cuda()
+    holder = {}
+    ms_e = timed(lambda: holder.update(e=m.eloc(sp, want_logpsi=False)), steps, 0)
+    ms_g = timed(lambda: holder.update(O=m.grad(sp)), steps, 0)
+    ms_sr = timed(lambda: holder.update(d=m.sr_solve(holder["O"], holder["e"], 1e-6, 0.01)),
+                  steps, 0)
+    flops_gram = 8.0 * S * S * m.P / 2
+    return {"workload": name, "S": S, "P": m.P, "precision": w.precision,
+            "ms_eloc": ms_e, "ms_grad": ms_g, "ms_sr": ms_sr,
+            "gram_flops_lower_half": flops_gram,
+            "cholesky_flops": 8.0 * S ** 3 / 3,
+            "dtheta_norm": float(holder["d"].abs().pow(2).sum().sqrt().item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +236,8 @@ def main():
     ap.add_argument("--workload", default="6x6_fp32_eloc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the hot path is measured at "
@@ -273,11 +315,18 @@ def main():
     achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
     roofline = {"kernel": "eloc_bonds", "bound": "alu", "achieved": achieved,
                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                "traffic": counted_traffic() if args.workload == "6x6_fp32_eloc" else None,
                 "avg_launch_ms": avg_ms, "launches_per_step": launches_per_step,
                 "flops_per_launch": flops_per_launch,
                 "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()}}
 
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     errs = errors_vs_oracle(args.workload, params, spins_np, lp.cpu().numpy(), el.cpu().numpy())
     log(f"errors vs oracle: {errs}")
     result = {
@@ -302,6 +351,8 @@ def main():
         log(f"lanczos leg: {legs['lanczos_two_hop']['ms']:.2f} ms")
         legs["bf16x2_vs_fp32_8x8"] = leg_precision("8x8_k4_m256")
         log("precision leg done")
+        legs["sr_10x10"] = leg_sr()
+        log(f"sr leg: {legs['sr_10x10']['ms_sr']:.1f} ms")
     result["legs"] = legs
     del ws
     if cpu is not None:
