@@ -55,6 +55,10 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t
   out[3] = c3;
 }
 
+// reciprocal for the cache update (hardware rcp, ~1 ulp; the cache is rebuilt
+// from the spins every segment)
+__device__ __forceinline__ float rcp_fast(float v) { return __builtin_amdgcn_rcpf(v); }
+
 // position of the k-th (0-based) set bit of a 64-bit word (k < popcount)
 __device__ __forceinline__ int select64(uint64_t x, int k) {
   int pos = 0;
@@ -208,6 +212,180 @@ __global__ __launch_bounds__(1024) void sample_kernel(
   }
 }
 
+// Register-resident variant for one RBM with M <= 72 and G <= 512: each image
+// is held by SPLIT lanes (lanes l and l + 32 of a wavefront for SPLIT = 2),
+// each keeping its share of the image's tanh(theta) row in VGPRs for the whole
+// segment (loaded once from the refreshed cache), so a proposal reads only the
+// L2-resident site-pair rows.  The cache in HBM is not written back: the next
+// segment starts from a fresh refresh.
+template <typename R, int M, int SPLIT>
+__global__ __launch_bounds__(640) void sample_reg_kernel(
+    int N, int G, int n_htiles, const uint8_t* __restrict__ perminv,
+    const R* __restrict__ Tpair, const R* __restrict__ Fpair, const R* __restrict__ t,
+    const R* __restrict__ w, uint64_t* __restrict__ state, int n_prop, int phase, int64_t p0,
+    int n_skip_host, uint64_t seed, int8_t* __restrict__ spins_out, int64_t n_per_chain,
+    int64_t* __restrict__ acc_out, int8_t* __restrict__ cur_spins) {
+  constexpr int MH = M / SPLIT;                  // hidden units per lane
+  __shared__ double red[32];
+  const int64_t c = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = (blockDim.x + 63) >> 6;
+  const int g = SPLIT == 2 ? 32 * wv + (lane & 31) : tid;
+  const int part = SPLIT == 2 ? lane >> 5 : 0;
+  const bool active = g < G;
+  const bool lead = active && part == 0;
+  uint64_t lo = state[4 * c], hi = state[4 * c + 1], ctr = state[4 * c + 2];
+  const uint64_t id = state[4 * c + 3];
+  const uint64_t nmask_lo = N >= 64 ? ~0ull : ((1ull << N) - 1ull);
+  const uint64_t nmask_hi = N > 64 ? ((1ull << (N - 64)) - 1ull) : 0ull;
+  const int half = N / 2;
+  const bool valid = (__popcll(lo & nmask_lo) + __popcll(hi & nmask_hi) == half) &&
+                     ((lo & ~nmask_lo) == 0) && ((hi & ~nmask_hi) == 0);
+  const int n_skip = phase == 1 ? n_skip_host : 1;
+  const int gg = active ? g : 0;
+  const int h0 = part * MH;
+  R tr[MH], ti[MH];
+  R wr, wi;
+  {
+    const R* tc = t + (size_t)c * n_htiles * G * 16;
+#pragma unroll
+    for (int e = 0; e < MH; ++e) {
+      const int h = h0 + e;
+      tr[e] = tc[((size_t)(h >> 3) * G + gg) * 16 + 2 * (h & 7)];
+      ti[e] = tc[((size_t)(h >> 3) * G + gg) * 16 + 2 * (h & 7) + 1];
+    }
+    const R* wc = w + (size_t)c * G * 2;
+    wr = wc[2 * gg];
+    wi = wc[2 * gg + 1];
+  }
+  int64_t acc = 0;
+  for (int r = 0; r < n_prop && valid; ++r) {
+    uint64_t rnd[4];
+    philox4x64_10(ctr, 0, 0, 0, seed, id, rnd);
+    const int kup = (int)(((rnd[0] >> 11) * (uint64_t)half) >> 53);
+    const int kdn = (int)(((rnd[1] >> 11) * (uint64_t)half) >> 53);
+    const int i = select128(lo, hi, kup);
+    const int j = select128(~lo & nmask_lo, ~hi & nmask_hi, kdn);
+    const int l1 = perminv[(size_t)gg * N + i], l2 = perminv[(size_t)gg * N + j];
+    const R* Trow = Tpair + (((size_t)l1 * N + l2) * M + h0) * 2;
+    R pr = 1, pi = 0, qr = 1, qi = 0;
+#pragma unroll
+    for (int e = 0; e < MH; e += 2) {
+      R Tr = Trow[2 * e], Ti = Trow[2 * e + 1];
+      R a = fmaf_t(tr[e], Tr, fmaf_t(-ti[e], Ti, R(-1)));
+      R b = fmaf_t(tr[e], Ti, ti[e] * Tr);
+      R nr = fmaf_t(pr, a, -(pi * b));
+      pi = fmaf_t(pr, b, pi * a);
+      pr = nr;
+      Tr = Trow[2 * e + 2];
+      Ti = Trow[2 * e + 3];
+      a = fmaf_t(tr[e + 1], Tr, fmaf_t(-ti[e + 1], Ti, R(-1)));
+      b = fmaf_t(tr[e + 1], Ti, ti[e + 1] * Tr);
+      nr = fmaf_t(qr, a, -(qi * b));
+      qi = fmaf_t(qr, b, qi * a);
+      qr = nr;
+    }
+    R ppr = pr * qr - pi * qi, ppi = pr * qi + pi * qr;
+    if (SPLIT == 2) {
+      const R orr = __shfl_xor(ppr, 32, 64), oi = __shfl_xor(ppi, 32, 64);
+      const R nr = ppr * orr - ppi * oi;
+      ppi = ppr * oi + ppi * orr;
+      ppr = nr;
+    }
+    const R* f = Fpair + ((size_t)l1 * N + l2) * 2;
+    const R Rr = f[0] * ppr - f[1] * ppi, Ri = f[0] * ppi + f[1] * ppr;
+    double cr = 0.0, ci = 0.0;
+    if (lead) {
+      cr = (double)(wr * Rr - wi * Ri);
+      ci = (double)(wr * Ri + wi * Rr);
+    }
+    cr = wave_sum(cr);
+    ci = wave_sum(ci);
+    if (lane == 0) {
+      red[wv] = cr;
+      red[16 + wv] = ci;
+    }
+    __syncthreads();
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < nw; ++q) {
+      sr += red[q];
+      si += red[16 + q];
+    }
+    __syncthreads();
+    const double u = (double)(rnd[2] >> 11) * (1.0 / 9007199254740992.0);
+    const double den = sr * sr + si * si;
+    if (u < den) {
+      ++acc;
+#pragma unroll
+      for (int e = 0; e < MH; ++e) {
+        const R Tr = Trow[2 * e], Ti = Trow[2 * e + 1];
+        const R nr = tr[e] - Tr, ni = ti[e] - Ti;        // (t - T) / (1 - t T)
+        const R dr = R(1) - (tr[e] * Tr - ti[e] * Ti), di = -(tr[e] * Ti + ti[e] * Tr);
+        const R inv = rcp_fast(dr * dr + di * di);
+        tr[e] = (nr * dr + ni * di) * inv;
+        ti[e] = (ni * dr - nr * di) * inv;
+      }
+      const double qr2 = (double)(wr * Rr - wi * Ri), qi2 = (double)(wr * Ri + wi * Rr);
+      wr = (R)((qr2 * sr + qi2 * si) / den);
+      wi = (R)((qi2 * sr - qr2 * si) / den);
+      if (i < 64) lo ^= 1ull << i; else hi ^= 1ull << (i - 64);
+      if (j < 64) lo ^= 1ull << j; else hi ^= 1ull << (j - 64);
+    }
+    ++ctr;
+    if (phase == 1) {
+      const int64_t idx = p0 + r + 1;
+      if (idx % n_skip == 0) {
+        const int64_t m = idx / n_skip - 1;
+        if (m < n_per_chain && tid < N) {
+          const uint64_t bit = tid < 64 ? (lo >> tid) & 1ull : (hi >> (tid - 64)) & 1ull;
+          spins_out[((size_t)c * n_per_chain + m) * N + tid] = bit ? 1 : -1;
+        }
+      }
+    }
+  }
+  if (tid == 0) {
+    state[4 * c] = lo;
+    state[4 * c + 1] = hi;
+    state[4 * c + 2] = ctr;
+    acc_out[c] += valid ? acc : -((int64_t)1 << 40);
+  }
+  if (tid < N) {
+    const uint64_t bit = tid < 64 ? (lo >> tid) & 1ull : (hi >> (tid - 64)) & 1ull;
+    cur_spins[(size_t)c * N + tid] = bit ? 1 : -1;
+  }
+}
+
+template <typename R, int M, int SPLIT>
+hipError_t launch_reg(const nqs_ctx* c, int64_t n, const void* t, const void* w,
+                      uint64_t* state, int cnt, int phase, int64_t p0, int ns, uint64_t seed,
+                      int8_t* spins_out, int64_t n_per_chain, int64_t* acc, int8_t* cur,
+                      hipStream_t st) {
+  const int threads = SPLIT == 2 ? 64 * ((c->G + 31) / 32) : 64 * ((c->G + 63) / 64);
+  if (threads > 640) return hipErrorNotSupported;
+  sample_reg_kernel<R, M, SPLIT><<<(unsigned)n, threads, 0, st>>>(
+      c->N, c->G, c->n_htiles, c->dev.perminv, (const R*)c->par.Tpair, (const R*)c->par.Fpair,
+      (const R*)t, (const R*)w, state, cnt, phase, p0, ns, seed, spins_out, n_per_chain, acc,
+      cur);
+  return hipGetLastError();
+}
+
+// Dispatch to a register-resident instantiation, or hipErrorNotSupported.
+hipError_t try_reg(const nqs_ctx* c, int64_t n, const void* t, const void* w, uint64_t* state,
+                   int cnt, int phase, int64_t p0, int ns, uint64_t seed, int8_t* spins_out,
+                   int64_t n_per_chain, int64_t* acc, int8_t* cur, hipStream_t st) {
+  // FP32 only: the FP64 path (small lattices) stays on the cache-streaming kernel
+  if (c->K != 1 || c->G > 512 || c->prec == NQS_FP64) return hipErrorNotSupported;
+#define NQS_REG_CASE(MM, SP)                                                                 \
+  if (c->M == MM)                                                                            \
+    return launch_reg<float, MM, SP>(c, n, t, w, state, cnt, phase, p0, ns, seed, spins_out, \
+                                     n_per_chain, acc, cur, st);
+  NQS_REG_CASE(8, 1)
+  NQS_REG_CASE(16, 1)
+  NQS_REG_CASE(32, 2)
+  NQS_REG_CASE(72, 2)
+#undef NQS_REG_CASE
+  return hipErrorNotSupported;
+}
+
 __global__ void pack_kernel(const int8_t* __restrict__ spins, int64_t n, int N, uint64_t first,
                             uint64_t* __restrict__ state) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -351,18 +529,22 @@ nqs_status nqs_sample(nqs_ctx* c, int64_t n_chains, int64_t n_per_chain, int32_t
       hipError_t r = refresh();
       if (r != hipSuccess) return r;
       prof_begin(c, K_SAMPLE, st);
-      if (c->prec == NQS_FP64)
-        sample_kernel<double><<<(unsigned)n, threads, lds, st>>>(
-            c->N, c->G, c->K, c->M, c->n_htiles, c->dev.perminv, (const double*)c->par.Tpair,
-            (const double*)c->par.Fpair, (double*)t, (double*)w, chain_state, cnt, phase, p0,
-            ns_dev, ns_host, seed, spins_out, n_per_chain, acc, cur);
-      else
-        sample_kernel<float><<<(unsigned)n, threads, lds, st>>>(
-            c->N, c->G, c->K, c->M, c->n_htiles, c->dev.perminv, (const float*)c->par.Tpair,
-            (const float*)c->par.Fpair, (float*)t, (float*)w, chain_state, cnt, phase, p0,
-            ns_dev, ns_host, seed, spins_out, n_per_chain, acc, cur);
+      r = try_reg(c, (int64_t)n, t, w, chain_state, cnt, phase, p0, ns_host, seed, spins_out,
+                  n_per_chain, acc, cur, st);
+      if (r == hipErrorNotSupported) {
+        if (c->prec == NQS_FP64)
+          sample_kernel<double><<<(unsigned)n, threads, lds, st>>>(
+              c->N, c->G, c->K, c->M, c->n_htiles, c->dev.perminv, (const double*)c->par.Tpair,
+              (const double*)c->par.Fpair, (double*)t, (double*)w, chain_state, cnt, phase, p0,
+              ns_dev, ns_host, seed, spins_out, n_per_chain, acc, cur);
+        else
+          sample_kernel<float><<<(unsigned)n, threads, lds, st>>>(
+              c->N, c->G, c->K, c->M, c->n_htiles, c->dev.perminv, (const float*)c->par.Tpair,
+              (const float*)c->par.Fpair, (float*)t, (float*)w, chain_state, cnt, phase, p0,
+              ns_dev, ns_host, seed, spins_out, n_per_chain, acc, cur);
+        r = hipGetLastError();
+      }
       prof_end(c, K_SAMPLE, st);
-      r = hipGetLastError();
       if (r != hipSuccess) return r;
     }
     return hipSuccess;
