@@ -457,6 +457,8 @@ hipError_t launch_eloc_finish(const nqs_ctx* c, const int8_t* spins, int64_t S,
 hipError_t launch_twohop(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
                          const void* w, double* partial2, hipStream_t st) {
   if (S <= 0) return hipSuccess;
+  const hipError_t e = launch_twohop_reg(c, spins, S, t, w, partial2, st);
+  if (e != hipErrorNotSupported) return e;
   return c->prec == NQS_FP64 ? twohop_typed<double>(c, spins, S, t, w, partial2, st)
                              : twohop_typed<float>(c, spins, S, t, w, partial2, st);
 }

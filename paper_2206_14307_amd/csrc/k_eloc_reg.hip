@@ -185,6 +185,173 @@ hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t, 
   return hipGetLastError();
 }
 
+
+// Two-hop H^2 terms (Sec. 3.3) for single-RBM models with register-resident
+// tanh(theta) rows.  For exchanges b1 then b2 with signs s1, s2 (orientation
+// folded) and unsigned T1 = tanh D1, T2 = tanh D2:
+//   s1 s2 cosh(theta + s1 D1 + s2 D2)/(cosh theta cosh D1 cosh D2) = s2 A + T2 B,
+//   A = s1 + t T1,  B = s1 t + T1,
+// and (s1 s2)^M = 1, so the second-hop product is prod_h (s2 A_h + T2_h B_h)
+// and the first-hop product prod_h A_h.  One wavefront per (sample, first-hop
+// slot, 32-image tile); the +T table stays in LDS for the launch.
+template <typename R, int N, int M>
+__global__ __launch_bounds__(64 * kRegWaves) void twohop_reg_kernel(
+    const int8_t* __restrict__ spins, int64_t S, int G, int n_htiles,
+    const int32_t* __restrict__ bonds, const double* __restrict__ bond_J,
+    const int32_t* __restrict__ bmap, const R* __restrict__ t, const R* __restrict__ w,
+    const R* __restrict__ Tpm, const R* __restrict__ F, double* __restrict__ partial2) {
+  using Cfg = RegCfg<R, N, 1, M>;
+  constexpr int NB = Cfg::NB, ST = Cfg::STRIDE;
+  __shared__ __align__(16) R Tl[NB * ST];
+  __shared__ int16_t lists[kRegWaves][2][NB];
+  __shared__ int8_t rows[kRegWaves][N];
+  for (int idx = threadIdx.x; idx < NB * M; idx += blockDim.x) {
+    const int beta = idx / M, h = idx % M;
+    const R* src = Tpm + ((size_t)beta * 2 * M + h) * 2;
+    Tl[beta * ST + 2 * h] = src[0];
+    Tl[beta * ST + 2 * h + 1] = src[1];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ntiles = G / 32;
+  const int64_t n_items = S * NB * ntiles;
+  const int64_t stride = (int64_t)gridDim.x * kRegWaves;
+  int16_t* l1 = lists[wv][0];
+  int16_t* l2 = lists[wv][1];
+  int8_t* row2 = rows[wv];
+  for (int64_t item = (int64_t)blockIdx.x * kRegWaves + wv; item < n_items; item += stride) {
+    const int64_t s = item / ((int64_t)NB * ntiles);
+    const int slot = (int)((item / ntiles) % NB);
+    const int tile = (int)(item % ntiles);
+    const int8_t* srow = spins + s * N;
+    const int nc = build_list(srow, bonds, NB, l1, lane);
+    if (slot >= nc) continue;                            // wave-uniform
+    const int b1 = l1[slot];
+    const int i1 = bonds[2 * b1], j1 = bonds[2 * b1 + 1];
+    for (int i = lane; i < N; i += 64) row2[i] = srow[i];
+    wave_sync_lds();
+    if (lane == 0) {
+      row2[i1] = srow[j1];
+      row2[j1] = srow[i1];
+    }
+    wave_sync_lds();
+    const int nc2 = build_list(row2, bonds, NB, l2, lane);
+    double diag2 = 0.0;
+    for (int b = lane; b < NB; b += 64)
+      diag2 += 0.25 * bond_J[b] * (double)(row2[bonds[2 * b]] * row2[bonds[2 * b + 1]]);
+    diag2 = wave_sum(diag2);
+
+    const int g = tile * 32 + (lane & 31);
+    const int half = lane >> 5;
+    R tr[M], ti[M];
+#pragma unroll
+    for (int ht = 0; ht < M / 8; ++ht) {
+      const R* tp = t + (((size_t)s * n_htiles + ht) * G + g) * 16;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        tr[8 * ht + e] = tp[2 * e];
+        ti[8 * ht + e] = tp[2 * e + 1];
+      }
+    }
+    const R wr = w[((size_t)s * G + g) * 2], wi = w[((size_t)s * G + g) * 2 + 1];
+    const int v1 = bmap[(size_t)g * NB + b1];
+    const int beta1 = v1 >> 1;
+    const int s1b = -(int)srow[i1];
+    const int s1i = (v1 & 1) ? -s1b : s1b;
+    const R s1 = (R)s1i;
+    const R* T1 = Tl + beta1 * ST;
+    const R* f1 = F + ((size_t)beta1 * 2 + (s1i > 0 ? 0 : 1)) * 2;
+    const R g1r = f1[0] * wr - f1[1] * wi, g1i = f1[0] * wi + f1[1] * wr;   // w F1
+    double accr = 0.0, acci = 0.0;
+    if (half == 0) {
+      R pr = 1, pi = 0;
+#pragma unroll
+      for (int h = 0; h < M; ++h) {
+        const R Tr = T1[2 * h], Ti = T1[2 * h + 1];
+        const R a = fmaf_t(tr[h], Tr, fmaf_t(-ti[h], Ti, s1));
+        const R b = fmaf_t(tr[h], Ti, ti[h] * Tr);
+        const R nr = fmaf_t(pr, a, -(pi * b));
+        pi = fmaf_t(pr, b, pi * a);
+        pr = nr;
+      }
+      accr += diag2 * (double)(g1r * pr - g1i * pi);
+      acci += diag2 * (double)(g1r * pi + g1i * pr);
+    }
+    for (int i0 = half; i0 < nc2; i0 += 4) {
+      int beta[2], sidx[2];
+      R sgn[2], valid[2];
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const int ii = i0 + 2 * n;
+        valid[n] = ii < nc2 ? R(1) : R(0);
+        const int b = l2[ii < nc2 ? ii : i0];
+        const int v = bmap[(size_t)g * NB + b];
+        beta[n] = v >> 1;
+        const int s_b = -(int)row2[bonds[2 * b]];
+        const int sp = (v & 1) ? -s_b : s_b;
+        sgn[n] = (R)sp;
+        sidx[n] = sp > 0 ? 0 : 1;
+      }
+      const R* U0 = Tl + beta[0] * ST;
+      const R* U1 = Tl + beta[1] * ST;
+      R p0r = 1, p0i = 0, p1r = 1, p1i = 0;
+#pragma unroll
+      for (int h = 0; h < M; ++h) {
+        // keep the scheduler from hoisting every LDS load of the unrolled loop
+        if ((h & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+        const R Tr = T1[2 * h], Ti = T1[2 * h + 1];
+        const R Ar = fmaf_t(tr[h], Tr, fmaf_t(-ti[h], Ti, s1));
+        const R Ai = fmaf_t(tr[h], Ti, ti[h] * Tr);
+        const R Br = fmaf_t(s1, tr[h], Tr), Bi = fmaf_t(s1, ti[h], Ti);
+        {
+          const R Vr = U0[2 * h], Vi = U0[2 * h + 1];
+          const R fr = fmaf_t(Vr, Br, fmaf_t(-Vi, Bi, sgn[0] * Ar));
+          const R fi = fmaf_t(Vr, Bi, fmaf_t(Vi, Br, sgn[0] * Ai));
+          const R nr = fmaf_t(p0r, fr, -(p0i * fi));
+          p0i = fmaf_t(p0r, fi, p0i * fr);
+          p0r = nr;
+        }
+        {
+          const R Vr = U1[2 * h], Vi = U1[2 * h + 1];
+          const R fr = fmaf_t(Vr, Br, fmaf_t(-Vi, Bi, sgn[1] * Ar));
+          const R fi = fmaf_t(Vr, Bi, fmaf_t(Vi, Br, sgn[1] * Ai));
+          const R nr = fmaf_t(p1r, fr, -(p1i * fi));
+          p1i = fmaf_t(p1r, fi, p1i * fr);
+          p1r = nr;
+        }
+      }
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const R pr = n ? p1r : p0r, pi = n ? p1i : p0i;
+        const R* f2 = F + ((size_t)beta[n] * 2 + sidx[n]) * 2;
+        const R hr = f2[0] * g1r - f2[1] * g1i, hi = f2[0] * g1i + f2[1] * g1r;
+        accr += (double)(valid[n] * (hr * pr - hi * pi));
+        acci += (double)(valid[n] * (hr * pi + hi * pr));
+      }
+    }
+    accr = wave_sum(accr);
+    acci = wave_sum(acci);
+    if (lane == 0) {
+      const size_t o = ((size_t)s * NB + slot) * ntiles + tile;
+      partial2[2 * o] = accr;
+      partial2[2 * o + 1] = acci;
+    }
+    wave_sync_lds();
+  }
+}
+
+template <typename R, int N, int M>
+hipError_t run_twohop(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
+                      const void* w, double* partial2, hipStream_t st) {
+  const int64_t items = S * c->NB * (c->G / 32);
+  int64_t blocks = (items + kRegWaves - 1) / kRegWaves;
+  blocks = std::min<int64_t>(blocks, c->n_cu > 0 ? c->n_cu : 256);
+  twohop_reg_kernel<R, N, M><<<(unsigned)blocks, 64 * kRegWaves, 0, st>>>(
+      spins, S, c->G, c->n_htiles, c->dev.bonds, c->dev.bond_J, c->dev.bmap, (const R*)t,
+      (const R*)w, (const R*)c->par.Tpm, (const R*)c->par.F, partial2);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // Returns hipErrorNotSupported when no register-resident variant covers the model.
@@ -198,6 +365,18 @@ hipError_t launch_eloc_bonds_reg(const nqs_ctx* c, const int8_t* spins, int64_t 
     if (N == 16 && K == 1 && M == 16) return run<float, 16, 1, 16>(c, spins, S, t, w, partial, st);
     if (N == 36 && K == 1 && M == 72) return run<float, 36, 1, 72>(c, spins, S, t, w, partial, st);
     if (N == 36 && K == 2 && M == 16) return run<float, 36, 2, 16>(c, spins, S, t, w, partial, st);
+  }
+  return hipErrorNotSupported;
+}
+
+hipError_t launch_twohop_reg(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
+                             const void* w, double* partial2, hipStream_t st) {
+  if (c->K != 1) return hipErrorNotSupported;
+  if (c->prec == NQS_FP64) {
+    if (c->N == 16 && c->M == 16) return run_twohop<double, 16, 16>(c, spins, S, t, w, partial2, st);
+  } else {
+    if (c->N == 16 && c->M == 16) return run_twohop<float, 16, 16>(c, spins, S, t, w, partial2, st);
+    if (c->N == 36 && c->M == 72) return run_twohop<float, 36, 72>(c, spins, S, t, w, partial2, st);
   }
   return hipErrorNotSupported;
 }

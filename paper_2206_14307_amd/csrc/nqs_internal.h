@@ -131,6 +131,8 @@ hipError_t launch_eloc_finish(const nqs_ctx* c, const int8_t* spins, int64_t S,
 // Two-hop: partial2[s][slot][tile] for e2 (slot = index in the antiparallel list).
 hipError_t launch_twohop(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
                          const void* w, double* partial2, hipStream_t st);
+hipError_t launch_twohop_reg(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
+                             const void* w, double* partial2, hipStream_t st);
 hipError_t launch_twohop_finish(const nqs_ctx* c, const int8_t* spins, int64_t S,
                                 const double* partial2, double* e1e2, hipStream_t st);
 hipError_t launch_moments(const double* e1e2, const double* logpsi, int64_t S, int exact,
