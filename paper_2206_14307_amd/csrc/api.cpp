@@ -149,10 +149,22 @@ nqs_status upload(nqs_ctx* c, T** dst, const std::vector<T>& src) {
   return NQS_OK;
 }
 
+// Rebuild the parameter tables and read back whether the reciprocal form of
+// the exchange factors is in range for these parameters (synchronous).
+hipError_t prep_tables(nqs_ctx* c, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(c->par.flag + 1, 0, 8, st);
+  if (e == hipSuccess) e = launch_prep(c, st);
+  double bad = 1.0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, c->par.flag + 1, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  c->par.recip_ok = e == hipSuccess && bad == 0.0;
+  return e;
+}
+
 void free_all(nqs_ctx* c) {
   void* ptrs[] = {c->dev.perm, c->dev.perminv, c->dev.bonds, c->dev.bond_J, c->dev.bmap, c->dev.chi,
                   c->par.params, c->par.wfrag, c->par.bias, c->par.avec, c->par.Tpm,
-                  c->par.F, c->par.Tpair, c->par.Fpair, c->par.flag};
+                  c->par.F, c->par.Tpair, c->par.Fpair, c->par.Tdir, c->par.Urec, c->par.flag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -247,6 +259,8 @@ nqs_status nqs_create(const nqs_model_desc* d, nqs_ctx** out) {
                 {&c->par.F, (size_t)c->K * c->NB * 2 * 2 * rs},
                 {&c->par.Tpair, (size_t)c->N * c->N * c->KM * 2 * rs},
                 {&c->par.Fpair, (size_t)c->K * c->N * c->N * 2 * rs},
+                {&c->par.Tdir, (size_t)c->NB * (2 * c->KM + 18 * c->K) * rs},
+                {&c->par.Urec, (size_t)c->NB * (2 * c->KM + 18 * c->K) * rs},
                 {(void**)&c->par.flag, 16}};
   for (auto& a : allocs) {
     if (st != NQS_OK) break;
@@ -254,8 +268,7 @@ nqs_status nqs_create(const nqs_model_desc* d, nqs_ctx** out) {
   }
   if (st == NQS_OK && hipMemset(c->par.params, 0, (size_t)c->P * 16) != hipSuccess)
     st = NQS_ERR_DEVICE;
-  if (st == NQS_OK && launch_prep(c, nullptr) != hipSuccess) st = NQS_ERR_DEVICE;
-  if (st == NQS_OK && hipDeviceSynchronize() != hipSuccess) st = NQS_ERR_DEVICE;
+  if (st == NQS_OK && prep_tables(c, nullptr) != hipSuccess) st = NQS_ERR_DEVICE;
   if (st != NQS_OK) {
     free_all(c);
     delete c;
@@ -291,8 +304,7 @@ nqs_status nqs_set_params(nqs_ctx* c, const double* params, hipStream_t st) {
   if ((e = hipMemcpyAsync(c->par.params, params, (size_t)c->P * 16, hipMemcpyDeviceToDevice, st)) !=
       hipSuccess)
     return hip_fail(c, e, "memcpy params");
-  if ((e = launch_prep(c, st)) != hipSuccess) return hip_fail(c, e, "prep");
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "sync");
+  if ((e = prep_tables(c, st)) != hipSuccess) return hip_fail(c, e, "prep");
   return NQS_OK;
 }
 

@@ -5,12 +5,18 @@
 // runs on 16x16 MFMA exactly as in k_theta.hip, the log 2cosh / tanh
 // epilogue leaves tanh(theta) in the MFMA output layout -- lane (q, c) holds
 // hidden units 8 ht + 2q, 8 ht + 2q + 1 of image c -- and never goes to HBM.
-// Each bond-exchange product prod_h (s + t_h T_h) (sign folding as in
-// k_eloc_reg.hip) is split four ways over the q lanes of an image and joined
-// with two cross-lane complex multiplications.
+// Each bond-exchange product F_s prod_h (s + t_h T_h) (sign folding as in
+// k_eloc_reg.hip) is split into eight streams, two per q lane of an image;
+// each stream starts from a tabulated value (the bond prefactor F_s sits in
+// stream 0) and the four q lanes are joined by gfx950 row swaps
+// (v_permlane16_swap / v_permlane32_swap), which serve the two bonds of a
+// pass at once.  When the parameters allow it (range check at parameter
+// upload) the factors are taken in the reciprocal form T_h (t_h + s / T_h):
+// the streams start from the product of their T_h and multiply t_h + s U_h,
+// 6 VALU operations per factor instead of 8.
 //
-// The normalisation of the image weights is wave-local: with m the largest
-// Re L over the wave's images, u_kg = chi_g exp(L_kg - m), the wave emits
+// The normalisation of the image weights is wave-local: with m a shift common
+// to the wave's images, u_kg = chi_g exp(L_kg - m), the wave emits
 // (m, sum u, sum_b (J_b/2) sum u R) and a per-sample finish kernel combines
 // the column blocks: log psi = M + log sum e^{m-M} den,
 // E_loc = diag + sum e^{m-M} Q / sum e^{m-M} den.
@@ -25,7 +31,7 @@ namespace {
 
 constexpr int kFusedWaves = 8;
 
-template <int N, int PREC, int K, int M>
+template <int N, int PREC, int K, int M, bool RECIP>
 struct FusedCfg {
   using T = ThetaTraits<PREC>;
   using R = typename T::R;
@@ -33,22 +39,33 @@ struct FusedCfg {
   static constexpr int KM = K * M;
   static constexpr int NHT = KM / 8;
   static constexpr int NK = nk_of<N, PREC>();
-  static constexpr int ST = 2 * KM + (sizeof(R) == 4 ? 4 : 2);
+  // LDS row of bond beta: tanh(D) (direct) or 1/tanh(D) (reciprocal) per
+  // hidden unit, then 18 K stream start values; the row stride is an odd
+  // number of 16-byte units
+  static constexpr int ROW = 2 * KM + 18 * K;
+  static constexpr int ST16 = ((ROW * (int)sizeof(R) + 15) / 16) | 1;
+  static constexpr int ST = ST16 * 16 / (int)sizeof(R);
   static constexpr size_t LDS = (size_t)NB * ST * sizeof(R) +
                                 (size_t)NHT * NK * 64 * sizeof(typename T::AFrag) +
                                 (size_t)kFusedWaves * NB * 2;
 };
 
+// Anti-aligned bonds of the sample: entry b | 0x8000 when s_b = -sigma_p = -1
+// for bond (p, q).
 __device__ __forceinline__ int fused_list(const int8_t* srow, const int32_t* bonds, int NB,
-                                          int16_t* list, int lane) {
+                                          uint16_t* list, int lane) {
   int n = 0;
   for (int base = 0; base < NB; base += 64) {
     const int b = base + lane;
     bool anti = false;
-    if (b < NB) anti = srow[bonds[2 * b]] != srow[bonds[2 * b + 1]];
+    int sp = 0;
+    if (b < NB) {
+      sp = srow[bonds[2 * b]];
+      anti = sp != srow[bonds[2 * b + 1]];
+    }
     const unsigned long long m = __ballot(anti);
     const int pos = __popcll(m & ((1ull << lane) - 1ull));
-    if (anti) list[n + pos] = (int16_t)b;
+    if (anti) list[n + pos] = (uint16_t)(b | (sp > 0 ? 0x8000 : 0));
     n += __popcll(m);
   }
   wave_sync_lds();
@@ -64,42 +81,85 @@ __device__ __forceinline__ void step_sp(R& pr, R& pi, R s, R tr, R ti, R Tr, R T
   pr = nr;
 }
 
-// complex product over the four q lanes of one image (xor 16, xor 32)
+// p *= (t + s U), the reciprocal form of the same factor up to T
 template <typename R>
-__device__ __forceinline__ void qprod(R& pr, R& pi) {
-#pragma unroll
-  for (int o = 16; o <= 32; o <<= 1) {
-    const R orr = __shfl_xor(pr, o, 64), oi = __shfl_xor(pi, o, 64);
-    const R nr = pr * orr - pi * oi;
-    pi = pr * oi + pi * orr;
-    pr = nr;
-  }
+__device__ __forceinline__ void step_rc(R& pr, R& pi, R s, R tr, R ti, R Ur, R Ui) {
+  const R a = fmaf_t(s, Ur, tr);
+  const R b = fmaf_t(s, Ui, ti);
+  const R nr = fmaf_t(pr, a, -(pi * b));
+  pi = fmaf_t(pr, b, pi * a);
+  pr = nr;
 }
 
-template <int N, int PREC, int K, int M>
+// Row swaps of gfx950 (a row is 16 lanes; rows 0..3 are q = 0..3):
+// swap16(x, y): x <- [x0 y0 x2 y2], y <- [x1 y1 x3 y3];
+// swap32(x, y): x <- [x0 x1 y0 y1], y <- [x2 x3 y2 y3].
+__device__ __forceinline__ void swap16(float& x, float& y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap32(float& x, float& y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap16(double& x, double& y) {
+  const unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)bx, (unsigned)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(bx >> 32), (unsigned)(by >> 32),
+                                                   false, false);
+  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ void swap32(double& x, double& y) {
+  const unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32),
+                                                   false, false);
+  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
+// Complex products over the four q rows of two bonds at once: on entry p
+// holds bond 0's and o bond 1's per-row partial products; on exit p holds the
+// full product of bond 0 in rows 0, 2 and of bond 1 in rows 1, 3.
+template <typename R>
+__device__ __forceinline__ void qprod_pair(R& pr, R& pi, R orr, R oi) {
+  swap16(pr, orr);
+  swap16(pi, oi);
+  R vr = pr * orr - pi * oi, vi = pr * oi + pi * orr;
+  R wr = vr, wi = vi;
+  swap32(vr, wr);
+  swap32(vi, wi);
+  pr = vr * wr - vi * wi;
+  pi = vr * wi + vi * wr;
+}
+
+template <int N, int PREC, int K, int M, bool RECIP>
 __global__ __launch_bounds__(64 * kFusedWaves) void eloc_fused_kernel(
     const int8_t* __restrict__ spins, int64_t S, const uint8_t* __restrict__ perm, int G,
     const typename ThetaTraits<PREC>::AFrag* __restrict__ wfrag,
     const typename ThetaTraits<PREC>::R* __restrict__ bias,
     const typename ThetaTraits<PREC>::R* __restrict__ avec, const int32_t* __restrict__ bonds,
     const int32_t* __restrict__ bmap, const double* __restrict__ chi,
-    const typename ThetaTraits<PREC>::R* __restrict__ Tpm,
-    const typename ThetaTraits<PREC>::R* __restrict__ F, double* __restrict__ part) {
-  using Cfg = FusedCfg<N, PREC, K, M>;
+    const typename ThetaTraits<PREC>::R* __restrict__ Ttab, double* __restrict__ part) {
+  using Cfg = FusedCfg<N, PREC, K, M, RECIP>;
   using T = ThetaTraits<PREC>;
   using R = typename T::R;
   using AF = typename T::AFrag;
   constexpr int NB = Cfg::NB, KM = Cfg::KM, NHT = Cfg::NHT, NK = Cfg::NK, ST = Cfg::ST;
+  constexpr int ROW = Cfg::ROW;
   constexpr int TPR = M / 8;
   __shared__ __align__(16) R Tl[NB * ST];
   __shared__ __align__(16) AF Wl[NHT * NK * 64];
-  __shared__ int16_t lists[kFusedWaves][NB];
+  __shared__ uint16_t lists[kFusedWaves][NB];
 
-  for (int idx = threadIdx.x; idx < NB * KM; idx += blockDim.x) {
-    const int beta = idx / KM, h = idx % KM;
-    const R* src = Tpm + ((size_t)beta * 2 * KM + h) * 2;
-    Tl[beta * ST + 2 * h] = src[0];
-    Tl[beta * ST + 2 * h + 1] = src[1];
+  for (int idx = threadIdx.x; idx < NB * ROW; idx += blockDim.x) {
+    const int beta = idx / ROW, j = idx % ROW;
+    Tl[beta * ST + j] = Ttab[(size_t)beta * ROW + j];
   }
   for (int idx = threadIdx.x; idx < NHT * NK * 64; idx += blockDim.x) Wl[idx] = wfrag[idx];
   __syncthreads();
@@ -109,7 +169,7 @@ __global__ __launch_bounds__(64 * kFusedWaves) void eloc_fused_kernel(
   const int cbs = G / 16;
   const int64_t n_items = S * cbs;
   const int64_t stride = (int64_t)gridDim.x * kFusedWaves;
-  int16_t* list = lists[wv];
+  uint16_t* list = lists[wv];
 
   for (int64_t item = (int64_t)blockIdx.x * kFusedWaves + wv; item < n_items; item += stride) {
     const int64_t s = item / cbs;
@@ -122,7 +182,9 @@ __global__ __launch_bounds__(64 * kFusedWaves) void eloc_fused_kernel(
 
     // ---- theta on MFMA + epilogue: tanh(theta) stays in registers
     R tr[NHT * 2], ti[NHT * 2];
-    double Lr[K], Li[K];
+    double Er[K];        // Re a.x + sum |Re theta| + E ln 2 (exponent part of L)
+    R Pr_[K], Pi_[K];    // renormalised product of c_h, |P| in [1/16, 4)
+    R Ai_[K];            // Im a.x
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       R pr = R(1), pi = R(0);
@@ -167,93 +229,126 @@ __global__ __launch_bounds__(64 * kFusedWaves) void eloc_fused_kernel(
       axi += __shfl_xor(axi, 16, 64);
       axr += __shfl_xor(axr, 32, 64);
       axi += __shfl_xor(axi, 32, 64);
-      Lr[k] = axr + sax + (double)(R(0.5) * log_t(pr * pr + pi * pi)) +
-              (double)E * 0.69314718055994530942;
-      Li[k] = axi + (double)atan2_t(pi, pr);
+      Er[k] = axr + sax + (double)E * 0.69314718055994530942;
+      Pr_[k] = pr;
+      Pi_[k] = pi;
+      Ai_[k] = (R)axi;
     }
-    double mloc = Lr[0];
+    // u_kg = chi_g exp(L_kg - m) = chi_g e^{Er - m} P e^{i Im a.x}; any common
+    // shift m works, the largest Er keeps every u below 4 in magnitude
+    double mloc = Er[0];
 #pragma unroll
-    for (int k = 1; k < K; ++k) mloc = fmax(mloc, Lr[k]);
+    for (int k = 1; k < K; ++k) mloc = fmax(mloc, Er[k]);
     const double m = wave_max(mloc);
     const R ch = (R)chi[g];
     R ur[K], ui[K];
     double denr = 0.0, deni = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const R e = ch * exp_t((R)(Lr[k] - m));
+      const R e = ch * exp_t((R)(Er[k] - m));
       R sn, cs;
-      sincos_t((R)Li[k], &sn, &cs);
-      ur[k] = e * cs;
-      ui[k] = e * sn;
+      sincos_t(Ai_[k], &sn, &cs);
+      const R zr = Pr_[k] * cs - Pi_[k] * sn, zi = Pr_[k] * sn + Pi_[k] * cs;
+      ur[k] = e * zr;
+      ui[k] = e * zi;
       denr += (double)ur[k];
       deni += (double)ui[k];
     }
 
-    // ---- bond exchanges, two bonds per pass
-    double Qr = 0.0, Qi = 0.0;
-    for (int i0 = 0; i0 < nc; i0 += 2) {
-      int beta[2], sidx[2];
-      R sgn[2], valid[2];
+    // ---- bond exchanges, two bonds per pass; the next pass's map entries
+    // are loaded one pass ahead
+    double Qr[K], Qi[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) Qr[k] = Qi[k] = 0.0;
+    const int32_t* bm = bmap + (size_t)g * NB;
+    int en[2] = {0, 0}, vn[2] = {0, 0};
+    if (nc > 0) {
 #pragma unroll
       for (int n = 0; n < 2; ++n) {
-        const int ii = i0 + n;
-        valid[n] = ii < nc ? R(1) : R(0);
-        const int b = list[ii < nc ? ii : i0];
-        const int v = bmap[(size_t)g * NB + b];
-        beta[n] = v >> 1;
-        const int s_b = -(int)srow[bonds[2 * b]];
-        const int sp = (v & 1) ? -s_b : s_b;
-        sgn[n] = (R)sp;
-        sidx[n] = sp > 0 ? 0 : 1;
+        en[n] = list[n < nc ? n : 0];
+        vn[n] = bm[en[n] & 0x7fff];
       }
-      const R* T0 = Tl + beta[0] * ST + 4 * q;
-      const R* T1 = Tl + beta[1] * ST + 4 * q;
+    }
+    for (int i0 = 0; i0 < nc; i0 += 2) {
+      const int e0 = en[0], e1 = en[1], v0 = vn[0], v1 = vn[1];
+      if (i0 + 2 < nc) {
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          en[n] = list[i0 + 2 + n < nc ? i0 + 2 + n : i0 + 2];
+          vn[n] = bm[en[n] & 0x7fff];
+        }
+      }
+      // s = s_b, flipped when the image bond runs against its table orientation
+      const R sg0 = ((e0 >> 15) ^ (v0 & 1)) ? R(-1) : R(1);
+      const R sg1 = ((e1 >> 15) ^ (v1 & 1)) ? R(-1) : R(1);
+      const R* row0 = Tl + (v0 >> 1) * ST;
+      const R* row1 = Tl + (v1 >> 1) * ST;
+      const R* T0 = row0 + 4 * q;
+      const R* T1 = row1 + 4 * q;
+      const bool valid1 = i0 + 1 < nc;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        R a0r = 1, a0i = 0, b0r = 1, b0i = 0, a1r = 1, a1i = 0, b1r = 1, b1i = 0;
+        // stream starts: (a re, a im, b re, b im) of lane q; stream 0 (q = 0,
+        // a) carries F_s, whose s = -1 value is stored after the others
+        const R* s0 = row0 + 2 * KM + 16 * k + 4 * q;
+        const R* s1 = row1 + 2 * KM + 16 * k + 4 * q;
+        const R* n0 = (q == 0 && sg0 < R(0)) ? row0 + 2 * KM + 16 * K + 2 * k : s0;
+        const R* n1 = (q == 0 && sg1 < R(0)) ? row1 + 2 * KM + 16 * K + 2 * k : s1;
+        R a0r = n0[0], a0i = n0[1], b0r = s0[2], b0i = s0[3];
+        R a1r = n1[0], a1i = n1[1], b1r = s1[2], b1i = s1[3];
 #pragma unroll
         for (int tt = 0; tt < TPR; ++tt) {
           const int ht = k * TPR + tt;
+          R x0[4], x1[4];
           if constexpr (sizeof(R) == 4) {
-            const float4 x0 = *reinterpret_cast<const float4*>(T0 + 16 * ht);
-            const float4 x1 = *reinterpret_cast<const float4*>(T1 + 16 * ht);
-            step_sp<R>(a0r, a0i, sgn[0], tr[2 * ht], ti[2 * ht], x0.x, x0.y);
-            step_sp<R>(b0r, b0i, sgn[0], tr[2 * ht + 1], ti[2 * ht + 1], x0.z, x0.w);
-            step_sp<R>(a1r, a1i, sgn[1], tr[2 * ht], ti[2 * ht], x1.x, x1.y);
-            step_sp<R>(b1r, b1i, sgn[1], tr[2 * ht + 1], ti[2 * ht + 1], x1.z, x1.w);
+            const float4 u0 = *reinterpret_cast<const float4*>(T0 + 16 * ht);
+            const float4 u1 = *reinterpret_cast<const float4*>(T1 + 16 * ht);
+            x0[0] = u0.x; x0[1] = u0.y; x0[2] = u0.z; x0[3] = u0.w;
+            x1[0] = u1.x; x1[1] = u1.y; x1[2] = u1.z; x1[3] = u1.w;
           } else {
-            const double2 x0 = *reinterpret_cast<const double2*>(T0 + 16 * ht);
-            const double2 y0 = *reinterpret_cast<const double2*>(T0 + 16 * ht + 2);
-            const double2 x1 = *reinterpret_cast<const double2*>(T1 + 16 * ht);
-            const double2 y1 = *reinterpret_cast<const double2*>(T1 + 16 * ht + 2);
-            step_sp<R>(a0r, a0i, sgn[0], tr[2 * ht], ti[2 * ht], x0.x, x0.y);
-            step_sp<R>(b0r, b0i, sgn[0], tr[2 * ht + 1], ti[2 * ht + 1], y0.x, y0.y);
-            step_sp<R>(a1r, a1i, sgn[1], tr[2 * ht], ti[2 * ht], x1.x, x1.y);
-            step_sp<R>(b1r, b1i, sgn[1], tr[2 * ht + 1], ti[2 * ht + 1], y1.x, y1.y);
+            const double2 u0 = *reinterpret_cast<const double2*>(T0 + 16 * ht);
+            const double2 w0 = *reinterpret_cast<const double2*>(T0 + 16 * ht + 2);
+            const double2 u1 = *reinterpret_cast<const double2*>(T1 + 16 * ht);
+            const double2 w1 = *reinterpret_cast<const double2*>(T1 + 16 * ht + 2);
+            x0[0] = u0.x; x0[1] = u0.y; x0[2] = w0.x; x0[3] = w0.y;
+            x1[0] = u1.x; x1[1] = u1.y; x1[2] = w1.x; x1[3] = w1.y;
+          }
+          if constexpr (RECIP) {
+            step_rc<R>(a0r, a0i, sg0, tr[2 * ht], ti[2 * ht], x0[0], x0[1]);
+            step_rc<R>(b0r, b0i, sg0, tr[2 * ht + 1], ti[2 * ht + 1], x0[2], x0[3]);
+            step_rc<R>(a1r, a1i, sg1, tr[2 * ht], ti[2 * ht], x1[0], x1[1]);
+            step_rc<R>(b1r, b1i, sg1, tr[2 * ht + 1], ti[2 * ht + 1], x1[2], x1[3]);
+          } else {
+            step_sp<R>(a0r, a0i, sg0, tr[2 * ht], ti[2 * ht], x0[0], x0[1]);
+            step_sp<R>(b0r, b0i, sg0, tr[2 * ht + 1], ti[2 * ht + 1], x0[2], x0[3]);
+            step_sp<R>(a1r, a1i, sg1, tr[2 * ht], ti[2 * ht], x1[0], x1[1]);
+            step_sp<R>(b1r, b1i, sg1, tr[2 * ht + 1], ti[2 * ht + 1], x1[2], x1[3]);
           }
         }
         R p0r = a0r * b0r - a0i * b0i, p0i = a0r * b0i + a0i * b0r;
-        R p1r = a1r * b1r - a1i * b1i, p1i = a1r * b1i + a1i * b1r;
-        qprod(p0r, p0i);
-        qprod(p1r, p1i);
-        if (q == 0) {
-          const R* f0 = F + (((size_t)k * NB + beta[0]) * 2 + sidx[0]) * 2;
-          const R* f1 = F + (((size_t)k * NB + beta[1]) * 2 + sidx[1]) * 2;
-          const R g0r = f0[0] * ur[k] - f0[1] * ui[k], g0i = f0[0] * ui[k] + f0[1] * ur[k];
-          const R g1r = f1[0] * ur[k] - f1[1] * ui[k], g1i = f1[0] * ui[k] + f1[1] * ur[k];
-          Qr += (double)(valid[0] * (g0r * p0r - g0i * p0i)) +
-                (double)(valid[1] * (g1r * p1r - g1i * p1i));
-          Qi += (double)(valid[0] * (g0r * p0i + g0i * p0r)) +
-                (double)(valid[1] * (g1r * p1i + g1i * p1r));
-        }
+        const R p1r = a1r * b1r - a1i * b1i, p1i = a1r * b1i + a1i * b1r;
+        qprod_pair(p0r, p0i, p1r, p1i);
+        // rows 0, 2: bond 0; rows 1, 3: bond 1 (absent on an odd tail)
+        const bool use = !(q & 1) || valid1;
+        Qr[k] += use ? (double)p0r : 0.0;
+        Qi[k] += use ? (double)p0i : 0.0;
       }
     }
+    // every bond was summed twice (rows 0 and 2, or 1 and 3)
+    double qr = 0.0, qi = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      qr += (double)ur[k] * Qr[k] - (double)ui[k] * Qi[k];
+      qi += (double)ur[k] * Qi[k] + (double)ui[k] * Qr[k];
+    }
+    qr *= 0.5;
+    qi *= 0.5;
     if (q != 0) {
       denr = 0.0;
       deni = 0.0;
     }
-    Qr = wave_sum(Qr);
-    Qi = wave_sum(Qi);
+    qr = wave_sum(qr);
+    qi = wave_sum(qi);
     denr = wave_sum(denr);
     deni = wave_sum(deni);
     if (lane == 0) {
@@ -261,8 +356,8 @@ __global__ __launch_bounds__(64 * kFusedWaves) void eloc_fused_kernel(
       o[0] = m;
       o[1] = denr;
       o[2] = deni;
-      o[3] = Qr;
-      o[4] = Qi;
+      o[3] = qr;
+      o[4] = qi;
       o[5] = 0.0;
     }
     wave_sync_lds();
@@ -308,7 +403,7 @@ __global__ __launch_bounds__(64) void fused_finish_kernel(
   }
 }
 
-template <int N, int PREC, int K, int M>
+template <int N, int PREC, int K, int M, bool RECIP>
 hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, double* logpsi,
                double* eloc, int eloc_stride, hipStream_t st) {
   using T = ThetaTraits<PREC>;
@@ -317,10 +412,10 @@ hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, d
   const int64_t items = S * cbs;
   int64_t blocks = (items + kFusedWaves - 1) / kFusedWaves;
   blocks = std::min<int64_t>(blocks, c->n_cu > 0 ? c->n_cu : 256);
-  eloc_fused_kernel<N, PREC, K, M><<<(unsigned)blocks, 64 * kFusedWaves, 0, st>>>(
+  eloc_fused_kernel<N, PREC, K, M, RECIP><<<(unsigned)blocks, 64 * kFusedWaves, 0, st>>>(
       spins, S, c->dev.perm, c->G, (const typename T::AFrag*)c->par.wfrag, (const R*)c->par.bias,
-      (const R*)c->par.avec, c->dev.bonds, c->dev.bmap, c->dev.chi, (const R*)c->par.Tpm,
-      (const R*)c->par.F, part);
+      (const R*)c->par.avec, c->dev.bonds, c->dev.bmap, c->dev.chi,
+      (const R*)(RECIP ? c->par.Urec : c->par.Tdir), part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   fused_finish_kernel<<<(unsigned)S, 64, 0, st>>>(spins, c->N, c->NB, cbs, c->dev.bonds,
@@ -330,13 +425,19 @@ hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, d
 
 constexpr size_t kLdsLimit = 160 * 1024;
 
+// The direct form decides whether a model runs fused at all (the workspace
+// depends on that, not on the parameters); the reciprocal form runs when its
+// range check passed for the current parameters and its table fits in LDS.
 template <int N, int PREC, int K, int M>
 hipError_t run_if_fits(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part,
                        double* logpsi, double* eloc, int es, hipStream_t st) {
-  if constexpr (FusedCfg<N, PREC, K, M>::LDS <= kLdsLimit)
-    return run<N, PREC, K, M>(c, spins, S, part, logpsi, eloc, es, st);
-  else
+  if constexpr (FusedCfg<N, PREC, K, M, false>::LDS > kLdsLimit) {
     return hipErrorNotSupported;
+  } else {
+    if constexpr (FusedCfg<N, PREC, K, M, true>::LDS <= kLdsLimit)
+      if (c->par.recip_ok) return run<N, PREC, K, M, true>(c, spins, S, part, logpsi, eloc, es, st);
+    return run<N, PREC, K, M, false>(c, spins, S, part, logpsi, eloc, es, st);
+  }
 }
 
 template <int N, int K, int M>
@@ -352,9 +453,9 @@ hipError_t run_prec(const nqs_ctx* c, const int8_t* spins, int64_t S, double* pa
 template <int N, int K, int M>
 bool fits(int prec) {
   switch (prec) {
-    case NQS_FP64: return FusedCfg<N, NQS_FP64, K, M>::LDS <= kLdsLimit;
-    case NQS_FP32: return FusedCfg<N, NQS_FP32, K, M>::LDS <= kLdsLimit;
-    default: return FusedCfg<N, NQS_BF16X2, K, M>::LDS <= kLdsLimit;
+    case NQS_FP64: return FusedCfg<N, NQS_FP64, K, M, false>::LDS <= kLdsLimit;
+    case NQS_FP32: return FusedCfg<N, NQS_FP32, K, M, false>::LDS <= kLdsLimit;
+    default: return FusedCfg<N, NQS_BF16X2, K, M, false>::LDS <= kLdsLimit;
   }
 }
 

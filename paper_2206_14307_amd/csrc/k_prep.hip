@@ -123,6 +123,92 @@ __global__ void prep_T_kernel(const double2* p, int Prbm, int M, int N, int KM, 
   row[2 * KM + 2 * h + 1] = (R)(-t.y);
 }
 
+// Bond rows of the fused E_loc kernel.  The hidden units of RBM k are split
+// into eight lane streams h = kM + 8j + r (r = 2q + u, j < M/8); the fused
+// kernel multiplies one stream per (lane, bond) and joins the eight streams
+// across lanes.  Two forms of the factor s + t T_h are tabulated:
+//   direct      row = [T_h, h < KM | start values]
+//   reciprocal  row = [U_h = 1/T_h | start values], s + t T = T (t + s U),
+// each with ROW = 2 KM + 18 K reals.  Start values (k, r) at 2KM + 16k + 2r
+// begin each stream's product: 1 (direct) or C_kr = prod_j T (reciprocal),
+// and stream r = 0 also carries the bond prefactor
+//   F_s = (J/2) e^{s A} prod_h cosh D_h   (A = a_p - a_q, bias term)
+// for s = +1; the s = -1 start of stream 0 sits at 2KM + 16K + 2k.
+// In the reciprocal form the partial products along a stream equal (finished
+// factors) x (suffix product of T), so that form is used only if every suffix
+// product |prod_{i >= j} T_i| lies in [2^lg_lo, 2^lg_hi]; flag[1] is set
+// otherwise.
+template <typename R>
+__global__ void prep_fused_rows_kernel(const double2* p, int Prbm, int K, int M, int N, int NB,
+                                       int use_bias, const int32_t* bonds, const double* bond_J,
+                                       double lg_lo, double lg_hi, R* Tdir, R* Urec,
+                                       double* flag) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= NB * K * 8) return;
+  const int beta = idx / (K * 8), k = (idx / 8) % K, r = idx % 8;
+  const int KM = K * M, TPR = M / 8, ROW = 2 * KM + 18 * K;
+  const int bp = bonds[2 * beta], bq = bonds[2 * beta + 1];
+  R* dir = Tdir + (size_t)beta * ROW;
+  R* rec = Urec + (size_t)beta * ROW;
+  double cr = 1.0, ci = 0.0, lg = 0.0;
+  bool ok = true;
+  for (int j = TPR - 1; j >= 0; --j) {
+    const int h = k * M + 8 * j + r;
+    const double2 wp = Wval(p, Prbm, M, N, h, bp);
+    const double2 wq = Wval(p, Prbm, M, N, h, bq);
+    const double2 t = ctanh64(wp.x - wq.x, wp.y - wq.y);
+    const double a2 = t.x * t.x + t.y * t.y;
+    const double nr = cr * t.x - ci * t.y;
+    ci = cr * t.y + ci * t.x;
+    cr = nr;
+    lg += 0.5 * log2(a2);                         // -inf for T = 0
+    ok = ok && lg >= lg_lo && lg <= lg_hi;
+    dir[2 * h] = (R)t.x;
+    dir[2 * h + 1] = (R)t.y;
+    rec[2 * h] = a2 > 0.0 ? (R)(t.x / a2) : (R)0;
+    rec[2 * h + 1] = a2 > 0.0 ? (R)(-t.y / a2) : (R)0;
+  }
+  if (!ok) flag[1] = 1.0;
+  double fr[2] = {1.0, 1.0}, fi[2] = {0.0, 0.0};
+  if (r == 0) {
+    double hr = 1.0, hi = 0.0;
+    for (int hh = 0; hh < M; ++hh) {
+      const double2 wp = Wval(p, Prbm, M, N, k * M + hh, bp);
+      const double2 wq = Wval(p, Prbm, M, N, k * M + hh, bq);
+      const double2 c = ccosh64(wp.x - wq.x, wp.y - wq.y);
+      const double nr = hr * c.x - hi * c.y;
+      hi = hr * c.y + hi * c.x;
+      hr = nr;
+    }
+    double ar = 0.0, ai = 0.0;
+    if (use_bias) {
+      const double2 ap = p[(size_t)k * Prbm + (size_t)M * N + bp];
+      const double2 aq = p[(size_t)k * Prbm + (size_t)M * N + bq];
+      ar = ap.x - aq.x;
+      ai = ap.y - aq.y;
+    }
+    const double hJ = 0.5 * bond_J[beta];
+    for (int s = 0; s < 2; ++s) {
+      const double sg = s == 0 ? 1.0 : -1.0;
+      const double2 e = cexp64(sg * ar, sg * ai);
+      fr[s] = hJ * (e.x * hr - e.y * hi);
+      fi[s] = hJ * (e.x * hi + e.y * hr);
+    }
+  }
+  const int st = 2 * KM + 16 * k + 2 * r;
+  dir[st] = (R)fr[0];
+  dir[st + 1] = (R)fi[0];
+  rec[st] = (R)(cr * fr[0] - ci * fi[0]);
+  rec[st + 1] = (R)(cr * fi[0] + ci * fr[0]);
+  if (r == 0) {
+    const int sn = 2 * KM + 16 * K + 2 * k;
+    dir[sn] = (R)fr[1];
+    dir[sn + 1] = (R)fi[1];
+    rec[sn] = (R)(cr * fr[1] - ci * fi[1]);
+    rec[sn + 1] = (R)(cr * fi[1] + ci * fr[1]);
+  }
+}
+
 // F[k][beta][s] = (J_beta / 2) exp(s A_beta) prod_h cosh(D_h,beta), s = +1 (0), -1 (1).
 template <typename R>
 __global__ void prep_F_kernel(const double2* p, int Prbm, int K, int M, int N, int NB, int use_bias,
@@ -239,6 +325,12 @@ hipError_t prep_typed(const nqs_ctx* c, hipStream_t st) {
   prep_F_kernel<R><<<(c->K * c->NB + 63) / 64, 64, 0, st>>>(
       p, c->P_rbm, c->K, c->M, c->N, c->NB, c->d.use_bias, c->dev.bonds, c->dev.bond_J,
       (R*)c->par.F);
+  // suffix-product range of the reciprocal form: FP32 keeps 2^+-96 clear of
+  // overflow and of the denormal range; FP64 2^+-900
+  const double lg = sizeof(R) == 4 ? 96.0 : 900.0;
+  prep_fused_rows_kernel<R><<<(c->NB * c->K * 8 + 63) / 64, 64, 0, st>>>(
+      p, c->P_rbm, c->K, c->M, c->N, c->NB, c->d.use_bias, c->dev.bonds, c->dev.bond_J, -lg, lg,
+      (R*)c->par.Tdir, (R*)c->par.Urec, c->par.flag);
   return hipGetLastError();
 }
 

@@ -50,7 +50,10 @@ struct ParamTables {
   void* F = nullptr;              // [K][NB][2] complex R: (J/2) exp(s A) prod_h cosh D
   void* Tpair = nullptr;          // [N][N][K*M] complex R: tanh(W_h,p - W_h,q) (sampler)
   void* Fpair = nullptr;          // [K][N][N] complex R: exp(-(a_p - a_q)) prod_h cosh(W_h,p - W_h,q)
-  double* flag = nullptr;         // [1] non-finite detector
+  void* Tdir = nullptr;           // [NB][2*K*M + 18*K] R: fused-kernel rows, direct form
+  void* Urec = nullptr;           // [NB][2*K*M + 18*K] R: fused-kernel rows, reciprocal form
+  double* flag = nullptr;         // [2] non-finite detector, reciprocal-form range violation
+  bool recip_ok = false;          // Urec usable for the current parameters
 };
 
 }  // namespace nqs

@@ -45,3 +45,22 @@ def nonzero_rows(model, params, spins, cut=30.0):
     import oracle
     w, _, _ = oracle.image_weights(model, params, spins)
     return np.abs(w).sum(axis=(1, 2)) < np.exp(cut)
+
+
+def reciprocal_form_in_range(model, params, lg=96.0):
+    """Whether the fused E_loc kernel may take the factors in the form
+    T_h (t_h + s / T_h): with the hidden units of one RBM split into eight
+    streams h = 8 j + r (j ascending), every suffix product of |tanh(D_h)|
+    along a stream, D_h = W_h,p - W_h,q for a bond (p, q), must lie in
+    [2^-lg, 2^lg].  Evaluated independently of the library to tell which form
+    a test exercises."""
+    M = model.n_hidden
+    for W, _, _ in model.split(params):
+        D = W[:, model.lat.bonds[:, 0]] - W[:, model.lat.bonds[:, 1]]      # [M, NB]
+        with np.errstate(divide="ignore"):
+            lg2 = np.log2(np.abs(np.tanh(D)))
+        for r in range(8):
+            suf = np.cumsum(lg2[r::8][::-1], axis=0)
+            if not ((suf >= -lg) & (suf <= lg)).all():
+                return False
+    return True

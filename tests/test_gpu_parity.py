@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from helpers import (TOL, max_logpsi_err, max_rel_err, max_row_rel_err, nonzero_rows,
-                     stress_params)
+                     reciprocal_form_in_range, stress_params)
 from workloads import WORKLOADS, draw_params, random_sz0_spins
 
 pytestmark = pytest.mark.gpu
@@ -241,3 +241,40 @@ def test_symmetry_invariance_at_full_size():
     rows = np.random.default_rng(1).choice(S, 6, replace=False)
     spn = sp[rows].cpu().numpy()
     assert max_rel_err(el.cpu().numpy()[rows], oracle.eloc_direct(om, p, spn)) < TOL["fp32"]
+
+
+# ------------------------------------------- both forms of the exchange factor
+
+def _flat_column(p, w, h):
+    """hidden unit h of every RBM gets W_h,p equal over sites: tanh(D_h) = 0
+    on every bond, so the reciprocal form is out of range"""
+    q = p.copy().reshape(w.n_rbm, -1)
+    for k in range(w.n_rbm):
+        q[k, h * w.N:(h + 1) * w.N] = q[k, h * w.N]
+    return q
+
+
+@pytest.mark.parametrize("case", ["drawn", "std1e-3", "std1e-4", "flat_column"])
+@pytest.mark.parametrize("name", ["4x4_fp64_exact", "6x6_fp32_eloc"])
+def test_eloc_both_factor_forms(name, case):
+    """The fused kernel takes the exchange factors as s + t T (direct) or as
+    T (t + s / T) (reciprocal, when every partial product stays in range);
+    both agree with the oracle, including parameters close to the range limit
+    (std 1e-3: suffix products near 2^-80 at M = 72) and just past it."""
+    w = WORKLOADS[name]
+    om = oracle.Model.from_workload(w)
+    if case == "drawn":
+        p = draw_params(w)
+    elif case == "flat_column":
+        p = _flat_column(draw_params(w), w, 3)
+    else:
+        p = stress_params(w, float(case[3:]), 12)
+    expect = {"drawn": True, "std1e-3": True, "std1e-4": w.n_hidden < 32, "flat_column": False}
+    lg = 900.0 if w.precision == "fp64" else 96.0
+    assert reciprocal_form_in_range(om, p, lg) == expect[case]
+    sp = random_sz0_spins(w.N, 21, 5)
+    m = make(w, p)
+    glp, gel = m.eloc(cuda(sp))
+    tol = TOL[w.precision]
+    assert max_logpsi_err(glp.cpu().numpy(), oracle.logpsi(om, p, sp)) < tol
+    assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp)) < tol
