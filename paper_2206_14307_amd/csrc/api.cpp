@@ -163,6 +163,7 @@ hipError_t prep_tables(nqs_ctx* c, hipStream_t st) {
 
 void free_all(nqs_ctx* c) {
   void* ptrs[] = {c->dev.perm, c->dev.perminv, c->dev.bonds, c->dev.bond_J, c->dev.bmap, c->dev.chi,
+                  c->dev.fmap, c->dev.frow,
                   c->par.params, c->par.wfrag, c->par.bias, c->par.avec, c->par.Tpm,
                   c->par.F, c->par.Tpair, c->par.Fpair, c->par.Tdir, c->par.Urec, c->par.flag};
   for (void* p : ptrs)
@@ -246,6 +247,20 @@ nqs_status nqs_create(const nqs_model_desc* d, nqs_ctx** out) {
   if (st == NQS_OK) st = upload(c, &c->dev.bond_J, c->geo.bond_J);
   if (st == NQS_OK) st = upload(c, &c->dev.bmap, c->geo.bmap);
   if (st == NQS_OK) st = upload(c, &c->dev.chi, c->geo.chi);
+  if (st == NQS_OK && eloc_fused_supported(c)) {
+    // bank-conflict-free LDS rows for the fused kernel, else plain odd-stride rows
+    const int rb = c->prec == NQS_FP64 ? 8 : 4;
+    const int row16 = nqs::fused_row16(c->K, c->M, rb);
+    std::vector<int> addr = nqs::place_fused_rows(c->geo, row16, nqs::fused_cap16(c->NB, row16));
+    if (addr.empty())
+      for (int b = 0; b < c->NB; ++b) addr.push_back(b * (row16 | 1));
+    std::vector<int32_t> frow(c->NB), fmap((size_t)c->G * c->NB);
+    for (int b = 0; b < c->NB; ++b) frow[b] = addr[b] * (16 / rb);
+    for (size_t i = 0; i < fmap.size(); ++i)
+      fmap[i] = 2 * frow[c->geo.bmap[i] >> 1] + (c->geo.bmap[i] & 1);
+    st = upload(c, &c->dev.frow, frow);
+    if (st == NQS_OK) st = upload(c, &c->dev.fmap, fmap);
+  }
   const size_t rs = real_size(c);
   const size_t frag_bytes = (size_t)c->n_htiles * c->nk * 64 * (c->prec == NQS_BF16X2 ? 16 : rs);
   struct {

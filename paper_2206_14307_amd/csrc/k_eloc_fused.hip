@@ -21,8 +21,9 @@
 // the column blocks: log psi = M + log sum e^{m-M} den,
 // E_loc = diag + sum e^{m-M} Q / sum e^{m-M} den.
 //
-// Persistent workgroups of 16 wavefronts keep the +tanh(D) bond table and
-// the W fragments in LDS for the whole launch.
+// Persistent workgroups keep the bond rows and the W fragments in LDS for the
+// whole launch; the rows are placed (host side) so that the 16 images of a q
+// row read distinct LDS bank groups.
 #include "theta_common.h"
 
 namespace nqs {
@@ -40,12 +41,11 @@ struct FusedCfg {
   static constexpr int NHT = KM / 8;
   static constexpr int NK = nk_of<N, PREC>();
   // LDS row of bond beta: tanh(D) (direct) or 1/tanh(D) (reciprocal) per
-  // hidden unit, then 18 K stream start values; the row stride is an odd
-  // number of 16-byte units
+  // hidden unit, then 18 K stream start values, at a host-chosen offset
   static constexpr int ROW = 2 * KM + 18 * K;
-  static constexpr int ST16 = ((ROW * (int)sizeof(R) + 15) / 16) | 1;
-  static constexpr int ST = ST16 * 16 / (int)sizeof(R);
-  static constexpr size_t LDS = (size_t)NB * ST * sizeof(R) +
+  static constexpr int CAP = fused_cap16(NB, fused_row16(K, M, (int)sizeof(R))) * 16 /
+                             (int)sizeof(R);
+  static constexpr size_t LDS = (size_t)CAP * sizeof(R) +
                                 (size_t)NHT * NK * 64 * sizeof(typename T::AFrag) +
                                 (size_t)kFusedWaves * NB * 2;
 };
@@ -144,22 +144,23 @@ __global__ __launch_bounds__(64 * kFusedWaves) void eloc_fused_kernel(
     const typename ThetaTraits<PREC>::AFrag* __restrict__ wfrag,
     const typename ThetaTraits<PREC>::R* __restrict__ bias,
     const typename ThetaTraits<PREC>::R* __restrict__ avec, const int32_t* __restrict__ bonds,
-    const int32_t* __restrict__ bmap, const double* __restrict__ chi,
+    const int32_t* __restrict__ fmap, const int32_t* __restrict__ frow,
+    const double* __restrict__ chi,
     const typename ThetaTraits<PREC>::R* __restrict__ Ttab, double* __restrict__ part) {
   using Cfg = FusedCfg<N, PREC, K, M, RECIP>;
   using T = ThetaTraits<PREC>;
   using R = typename T::R;
   using AF = typename T::AFrag;
-  constexpr int NB = Cfg::NB, KM = Cfg::KM, NHT = Cfg::NHT, NK = Cfg::NK, ST = Cfg::ST;
+  constexpr int NB = Cfg::NB, KM = Cfg::KM, NHT = Cfg::NHT, NK = Cfg::NK;
   constexpr int ROW = Cfg::ROW;
   constexpr int TPR = M / 8;
-  __shared__ __align__(16) R Tl[NB * ST];
+  __shared__ __align__(16) R Tl[Cfg::CAP];
   __shared__ __align__(16) AF Wl[NHT * NK * 64];
   __shared__ uint16_t lists[kFusedWaves][NB];
 
   for (int idx = threadIdx.x; idx < NB * ROW; idx += blockDim.x) {
     const int beta = idx / ROW, j = idx % ROW;
-    Tl[beta * ST + j] = Ttab[(size_t)beta * ROW + j];
+    Tl[frow[beta] + j] = Ttab[(size_t)beta * ROW + j];
   }
   for (int idx = threadIdx.x; idx < NHT * NK * 64; idx += blockDim.x) Wl[idx] = wfrag[idx];
   __syncthreads();
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(64 * kFusedWaves) void eloc_fused_kernel(
     double Qr[K], Qi[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) Qr[k] = Qi[k] = 0.0;
-    const int32_t* bm = bmap + (size_t)g * NB;
+    const int32_t* bm = fmap + (size_t)g * NB;
     int en[2] = {0, 0}, vn[2] = {0, 0};
     if (nc > 0) {
 #pragma unroll
@@ -281,8 +282,8 @@ __global__ __launch_bounds__(64 * kFusedWaves) void eloc_fused_kernel(
       // s = s_b, flipped when the image bond runs against its table orientation
       const R sg0 = ((e0 >> 15) ^ (v0 & 1)) ? R(-1) : R(1);
       const R sg1 = ((e1 >> 15) ^ (v1 & 1)) ? R(-1) : R(1);
-      const R* row0 = Tl + (v0 >> 1) * ST;
-      const R* row1 = Tl + (v1 >> 1) * ST;
+      const R* row0 = Tl + (v0 >> 1);
+      const R* row1 = Tl + (v1 >> 1);
       const R* T0 = row0 + 4 * q;
       const R* T1 = row1 + 4 * q;
       const bool valid1 = i0 + 1 < nc;
@@ -414,7 +415,7 @@ hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, d
   blocks = std::min<int64_t>(blocks, c->n_cu > 0 ? c->n_cu : 256);
   eloc_fused_kernel<N, PREC, K, M, RECIP><<<(unsigned)blocks, 64 * kFusedWaves, 0, st>>>(
       spins, S, c->dev.perm, c->G, (const typename T::AFrag*)c->par.wfrag, (const R*)c->par.bias,
-      (const R*)c->par.avec, c->dev.bonds, c->dev.bmap, c->dev.chi,
+      (const R*)c->par.avec, c->dev.bonds, c->dev.fmap, c->dev.frow, c->dev.chi,
       (const R*)(RECIP ? c->par.Urec : c->par.Tdir), part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -29,6 +29,17 @@ struct Geometry {
 bool build_geometry(int L, double J1, double J2, int kx, int ky, int irrep, Geometry& geo,
                     std::string& err);
 
+// LDS rows of the fused E_loc kernel: ROW = 2KM + 18K reals per bond, taking
+// row16 = ceil(ROW * sizeof(R) / 16) sixteen-byte units; the kernel reserves
+// fused_cap16 units.  place_fused_rows returns each bond row's start (units)
+// such that every 16-image column block reads distinct bank groups, or an
+// empty vector if the packing does not fit in cap16.
+constexpr int fused_row16(int K, int M, int real_bytes) {
+  return ((2 * K * M + 18 * K) * real_bytes + 15) / 16;
+}
+constexpr int fused_cap16(int NB, int row16) { return NB * (row16 | 1) + 256; }
+std::vector<int> place_fused_rows(const Geometry& geo, int row16, int cap16);
+
 // Device-side tables owned by the context.
 struct DeviceTables {
   uint8_t* perm = nullptr;        // [G][N]
@@ -37,6 +48,8 @@ struct DeviceTables {
   double* bond_J = nullptr;       // [NB]
   int32_t* bmap = nullptr;        // [G][NB]
   double* chi = nullptr;          // [G]
+  int32_t* fmap = nullptr;        // [G][NB] fused kernel: 2 * (LDS row offset in reals) + flip
+  int32_t* frow = nullptr;        // [NB]    fused kernel: LDS row offset in reals
 };
 
 // Parameter-derived tables (rebuilt by nqs_set_params).  "R" is double for

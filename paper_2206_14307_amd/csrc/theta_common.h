@@ -71,7 +71,8 @@ __device__ __forceinline__ void sincos_t(float v, float* s, float* c) {
   *c = ((qd + 1) & 2) ? -c0 : c0;
 }
 __device__ __forceinline__ double rcp_t(double v) { return 1.0 / v; }
-__device__ __forceinline__ float rcp_t(float v) { return __frcp_rn(v); }
+// hardware reciprocal (1 ulp)
+__device__ __forceinline__ float rcp_t(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ double log_t(double v) { return log(v); }
 __device__ __forceinline__ float log_t(float v) { return __logf(v); }
 __device__ __forceinline__ double atan2_t(double y, double x) { return atan2(y, x); }
