@@ -57,19 +57,64 @@ def n_antiparallel(spins, bonds):
     return (spins[:, bonds[:, 0]] != spins[:, bonds[:, 1]]).sum(axis=1)
 
 
-def counted_traffic(path=os.path.join(ROOT, "profiles", "eloc_fused_6x6_m72_hbm_counters.json")):
+COUNTER_JSON = os.path.join(ROOT, "profiles", "eloc_fused_6x6_m72_hbm_counters.json")
+COUNTER_SOURCES = ["k_eloc_fused.hip", "theta_common.h", "device_common.h", "nqs_internal.h",
+                   "lds_layout.cpp"]
+
+
+def source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2206_14307_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def write_counters(fetch_csv, write_csv, kernel="eloc_fused_kernel", copy_bytes=1 << 30):
+    """Summarise two rocprofv3 --pmc runs of `bench.py --copy-probe` (FETCH_SIZE,
+    then WRITE_SIZE, KiB per dispatch) into the committed counter JSON: the
+    kernel's mean per launch, scaled by what the counter reads for the 1 GiB
+    device copy the same run makes."""
+    import csv
+
+    def per_kernel(path, counter):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    f = per_kernel(fetch_csv, "FETCH_SIZE")
+    w = per_kernel(write_csv, "WRITE_SIZE")
+    kname = next(k for k in f if kernel in k)
+    copy = next(k for k in f if "copyBuffer" in k)
+    kib = copy_bytes / 1024.0
+    cf, cw = max(f[copy]), max(w[copy])
+    fk, wk = float(np.mean(f[kname])), float(np.mean(w[kname]))
+    d = {
+        "kernel": kname.replace("void ", "").replace("nqs::(anonymous namespace)::", "").split("(")[0],
+        "workload": "6x6 M=72 FP32, 262144 configurations, one launch",
+        "fetch_kib": fk, "write_kib": wk,
+        "copy_probe_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+        "fetch_scale": kib / cf, "write_scale": kib / cw,
+        "traffic_bytes_per_launch": 1024.0 * (fk * kib / cf + wk * kib / cw),
+        "kernel_source_sha256_16": source_hash(COUNTER_SOURCES),
+        "kernel_sources": COUNTER_SOURCES,
+    }
+    with open(COUNTER_JSON, "w") as fh:
+        json.dump(d, fh, indent=1)
+    return d
+
+
+def counted_traffic(path=COUNTER_JSON):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (copy-calibrated), or None when the kernel's
     sources have changed since the counters were taken."""
-    import hashlib
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    h = hashlib.sha256()
-    for f in d["kernel_sources"]:
-        h.update(open(os.path.join(ROOT, "paper_2206_14307_amd", "csrc", f), "rb").read())
-    if h.hexdigest()[:16] != d["kernel_source_sha256_16"]:
+    if source_hash(d["kernel_sources"]) != d["kernel_source_sha256_16"]:
         return None
     return d["traffic_bytes_per_launch"]
 
@@ -238,7 +283,12 @@ def main():
     ap.add_argument("--no-legs", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--write-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 counter CSVs into the committed JSON and exit")
     args = ap.parse_args()
+    if args.write_counters:
+        print(json.dumps(write_counters(*args.write_counters), indent=1))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the hot path is measured at "
                                    "--gpus 1 only (the multi-GPU sharding is a design, "
