@@ -53,11 +53,13 @@ ChunkSizes per_sample(const nqs_ctx* c) {
 
 // nqs_eloc runs the fused kernel when a register-resident variant covers the model
 bool fused_eloc(const nqs_ctx* c, int op) { return op == NQS_OP_ELOC && eloc_fused_supported(c); }
+bool fused_grad(const nqs_ctx* c, int op) { return op == NQS_OP_GRAD && grad_fused_supported(c); }
 size_t fused_part_bytes(const nqs_ctx* c) { return (size_t)(c->G / 16) * 6 * 8; }
 
 size_t chunk_bytes_per_sample(const nqs_ctx* c, int op) {
   const ChunkSizes z = per_sample(c);
   if (fused_eloc(c, op)) return fused_part_bytes(c) + 16;
+  if (fused_grad(c, op)) return 0;                 // no workspace
   switch (op) {
     case NQS_OP_LOGPSI: return z.L;
     case NQS_OP_ELOC: return z.L + z.w + z.t + z.partial;
@@ -111,6 +113,7 @@ Work plan(const nqs_ctx* c, int op, int64_t S, void* ws) {
   }
   const int64_t ch = chunk_of(c, op, S);
   wk.chunk = ch;
+  if (fused_grad(c, op)) return wk;
   if (fused_eloc(c, op)) {
     wk.partial = (double*)cv.take(fused_part_bytes(c) * ch);
     wk.lp = (double*)cv.take((size_t)16 * ch);
@@ -135,7 +138,7 @@ nqs_status check_common(nqs_ctx* c, const int8_t* spins, int64_t S, void* ws, si
   if (S < 0) return fail(c, NQS_ERR_ARG, "S must be >= 0");
   if (S > 0 && !spins) return fail(c, NQS_ERR_ARG, "spins is NULL");
   const size_t need = plan(c, op, S, nullptr).bytes;
-  if (S > 0 && (!ws || ws_bytes < need))
+  if (S > 0 && need > 0 && (!ws || ws_bytes < need))
     return fail(c, NQS_ERR_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
   return NQS_OK;
 }
@@ -428,6 +431,11 @@ nqs_status nqs_grad(nqs_ctx* c, const int8_t* spins, int64_t S, void* O_out, dou
   nqs_status s = check_common(c, spins, S, ws, ws_bytes, NQS_OP_GRAD);
   if (s != NQS_OK) return s;
   if (S > 0 && !O_out) return fail(c, NQS_ERR_ARG, "O_out is NULL");
+  if (fused_grad(c, NQS_OP_GRAD)) {
+    const hipError_t e =
+        NQS_RUN(c, K_GRAD, st, launch_grad_fused(c, spins, S, O_out, logpsi_out, st));
+    return e == hipSuccess ? NQS_OK : hip_fail(c, e, "grad launch");
+  }
   const Work wk = plan(c, NQS_OP_GRAD, S, ws);
   const size_t osz = (size_t)c->P * 2 * real_size(c);
   for (int64_t s0 = 0; s0 < S; s0 += wk.chunk) {

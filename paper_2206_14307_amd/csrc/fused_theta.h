@@ -1,0 +1,84 @@
+// Theta of one (sample, 16-image column block) on MFMA with the log 2cosh /
+// tanh epilogue (Sec. 3.1, Eq. (2)), shared by the fused E_loc and gradient
+// kernels.  Lane (q, c) = (lane / 16, lane % 16) handles image c of the block;
+// the W fragments are ordered so that every lane receives Re and Im theta of
+// hidden units 8 ht + 2q and 8 ht + 2q + 1 (ht = hidden tile).
+//
+// Per RBM k the block returns, for the lane's image,
+//   L_k = Er_k + log P_k + i Ai_k   (log psi_s of the image, up to i arg P_k)
+// with Er_k = Re a.x + sum_h |Re theta_h| + E ln 2 in FP64, P_k the product
+// of the c_h of the epilogue renormalised to |P_k| in [1/16, 4) (its exponent
+// E moved into Er_k) and Ai_k = Im a.x; tanh(theta) of the lane's hidden
+// units stays in tr / ti.  All four q lanes of an image end with the same
+// Er, P and Ai.
+#pragma once
+
+#include "theta_common.h"
+
+namespace nqs {
+
+template <int N, int PREC, int K, int M>
+__device__ __forceinline__ void theta_block(
+    const typename ThetaTraits<PREC>::AFrag* Wl, const typename ThetaTraits<PREC>::BFrag* bx,
+    const typename ThetaTraits<PREC>::R* bias, const typename ThetaTraits<PREC>::R* avec,
+    const int8_t* srow,
+    const uint8_t* prow, int lane, typename ThetaTraits<PREC>::R* tr,
+    typename ThetaTraits<PREC>::R* ti, double* Er, typename ThetaTraits<PREC>::R* Pr,
+    typename ThetaTraits<PREC>::R* Pi, typename ThetaTraits<PREC>::R* Ai) {
+  using T = ThetaTraits<PREC>;
+  using R = typename T::R;
+  constexpr int NK = nk_of<N, PREC>();
+  constexpr int TPR = M / 8;
+  const int q = lane >> 4;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    R pr = R(1), pi = R(0);
+    int pe = 0;
+    double sax = 0.0;
+#pragma unroll
+    for (int tt = 0; tt < TPR; ++tt) {
+      const int ht = k * TPR + tt;
+      typename T::Acc acc = typename T::Acc{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < NK; ++kk) acc = mfma(Wl[(ht * NK + kk) * 64 + lane], bx[kk], acc);
+      const int h0 = 8 * ht + 2 * q;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const R x = (R)acc[2 * u] + bias[2 * (h0 + u)];
+        const R y = (R)acc[2 * u + 1] + bias[2 * (h0 + u) + 1];
+        logcosh_step<R, true>(x, y, pr, pi, sax, tr[2 * ht + u], ti[2 * ht + u]);
+      }
+      if ((tt & 7) == 7) renorm(pr, pi, pe);
+    }
+    renorm(pr, pi, pe);
+    int E = pe;
+#pragma unroll
+    for (int o = 16; o <= 32; o <<= 1) {
+      const R orr = __shfl_xor(pr, o, 64), oi = __shfl_xor(pi, o, 64);
+      const R nr = pr * orr - pi * oi;
+      pi = pr * oi + pi * orr;
+      pr = nr;
+      E += __shfl_xor(E, o, 64);
+      sax += __shfl_xor(sax, o, 64);
+    }
+    double axr = 0.0, axi = 0.0;
+    const R* ak = avec + (size_t)k * N * 2;
+#pragma unroll
+    for (int jj = 0; jj < N / 4; ++jj) {
+      const int j = 4 * jj + q;
+      const double xj = 0.5 * (double)srow[prow[j]];
+      axr += xj * (double)ak[2 * j];
+      axi += xj * (double)ak[2 * j + 1];
+    }
+    axr += __shfl_xor(axr, 16, 64);
+    axi += __shfl_xor(axi, 16, 64);
+    axr += __shfl_xor(axr, 32, 64);
+    axi += __shfl_xor(axi, 32, 64);
+    Er[k] = axr + sax + (double)E * 0.69314718055994530942;
+    Pr[k] = pr;
+    Pi[k] = pi;
+    Ai[k] = (R)axi;
+  }
+}
+
+}  // namespace nqs

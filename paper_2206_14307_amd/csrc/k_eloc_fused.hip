@@ -24,7 +24,7 @@
 // Persistent workgroups keep the bond rows and the W fragments in LDS for the
 // whole launch; the rows are placed (host side) so that the 16 images of a q
 // row read distinct LDS bank groups.
-#include "theta_common.h"
+#include "fused_theta.h"
 
 namespace nqs {
 
@@ -183,58 +183,9 @@ __global__ __launch_bounds__(64 * kFusedWaves) void eloc_fused_kernel(
 
     // ---- theta on MFMA + epilogue: tanh(theta) stays in registers
     R tr[NHT * 2], ti[NHT * 2];
-    double Er[K];        // Re a.x + sum |Re theta| + E ln 2 (exponent part of L)
-    R Pr_[K], Pi_[K];    // renormalised product of c_h, |P| in [1/16, 4)
-    R Ai_[K];            // Im a.x
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      R pr = R(1), pi = R(0);
-      int pe = 0;
-      double sax = 0.0;
-#pragma unroll
-      for (int tt = 0; tt < TPR; ++tt) {
-        const int ht = k * TPR + tt;
-        typename T::Acc acc = typename T::Acc{0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < NK; ++kk) acc = mfma(Wl[(ht * NK + kk) * 64 + lane], bx[kk], acc);
-        const int h0 = 8 * ht + 2 * q;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const R x = (R)acc[2 * u] + bias[2 * (h0 + u)];
-          const R y = (R)acc[2 * u + 1] + bias[2 * (h0 + u) + 1];
-          logcosh_step<R, true>(x, y, pr, pi, sax, tr[2 * ht + u], ti[2 * ht + u]);
-        }
-        if ((tt & 7) == 7) renorm(pr, pi, pe);
-      }
-      renorm(pr, pi, pe);
-      int E = pe;
-#pragma unroll
-      for (int o = 16; o <= 32; o <<= 1) {
-        const R orr = __shfl_xor(pr, o, 64), oi = __shfl_xor(pi, o, 64);
-        const R nr = pr * orr - pi * oi;
-        pi = pr * oi + pi * orr;
-        pr = nr;
-        E += __shfl_xor(E, o, 64);
-        sax += __shfl_xor(sax, o, 64);
-      }
-      double axr = 0.0, axi = 0.0;
-      const R* ak = avec + (size_t)k * N * 2;
-#pragma unroll
-      for (int jj = 0; jj < N / 4; ++jj) {
-        const int j = 4 * jj + q;
-        const double xj = 0.5 * (double)srow[prow[j]];
-        axr += xj * (double)ak[2 * j];
-        axi += xj * (double)ak[2 * j + 1];
-      }
-      axr += __shfl_xor(axr, 16, 64);
-      axi += __shfl_xor(axi, 16, 64);
-      axr += __shfl_xor(axr, 32, 64);
-      axi += __shfl_xor(axi, 32, 64);
-      Er[k] = axr + sax + (double)E * 0.69314718055994530942;
-      Pr_[k] = pr;
-      Pi_[k] = pi;
-      Ai_[k] = (R)axi;
-    }
+    double Er[K];
+    R Pr_[K], Pi_[K], Ai_[K];
+    theta_block<N, PREC, K, M>(Wl, bx, bias, avec, srow, prow, lane, tr, ti, Er, Pr_, Pi_, Ai_);
     // u_kg = chi_g exp(L_kg - m) = chi_g e^{Er - m} P e^{i Im a.x}; any common
     // shift m works, the largest Er keeps every u below 4 in magnitude
     double mloc = Er[0];

@@ -139,6 +139,9 @@ hipError_t launch_eloc_bonds_reg(const nqs_ctx* c, const int8_t* spins, int64_t 
 // Fused theta + epilogue + bond exchanges (K*M <= 128 register-resident
 // variants); part holds S * (G/16) * 6 doubles.
 bool eloc_fused_supported(const nqs_ctx* c);
+bool grad_fused_supported(const nqs_ctx* c);
+hipError_t launch_grad_fused(const nqs_ctx* c, const int8_t* spins, int64_t S, void* O,
+                             double* logpsi, hipStream_t st);
 hipError_t launch_eloc_fused(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part,
                              double* logpsi, double* eloc, int eloc_stride, hipStream_t st);
 hipError_t launch_eloc_finish(const nqs_ctx* c, const int8_t* spins, int64_t S,
