@@ -220,8 +220,17 @@ def leg_grad(m, sp, S, G, K, steps=3):
                                 _stream()), "nqs_grad")
     ms = timed(run, steps, 1)
     del O
+    # algorithmic work: 8 N flops per (configuration, image, hidden unit),
+    # theta recompute included, on MFMA; the O write on HBM
+    N = int(sp.shape[1])
+    flops = 8.0 * N * S * G * m.n_rbm * m.n_hidden
+    o_bytes = S * m.P * (16 if m.precision == "fp64" else 8)
+    peak = 78.6 if m.precision == "fp64" else 157.3
     return {"S": S, "ms": ms, "configs_sym_images_per_s": S * K * G / (ms / 1e3),
-            "O_bytes": S * m.P * (16 if m.precision == "fp64" else 8)}
+            "O_bytes": o_bytes,
+            "roofline": {"bound": "mfma", "achieved": flops / (ms / 1e3) / 1e12, "peak": peak,
+                         "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / 1e12 / peak,
+                         "flops": flops, "hbm_GBps_O_write": o_bytes / (ms / 1e3) / 1e9}}
 
 
 def leg_precision(name, steps=2):

@@ -52,7 +52,9 @@ ChunkSizes per_sample(const nqs_ctx* c) {
 }
 
 // nqs_eloc runs the fused kernel when a register-resident variant covers the model
-bool fused_eloc(const nqs_ctx* c, int op) { return op == NQS_OP_ELOC && eloc_fused_supported(c); }
+bool fused_eloc(const nqs_ctx* c, int op) {
+  return op == NQS_OP_ELOC && (eloc_fused_supported(c) || eloc_wide_supported(c));
+}
 bool fused_grad(const nqs_ctx* c, int op) { return op == NQS_OP_GRAD && grad_fused_supported(c); }
 size_t fused_part_bytes(const nqs_ctx* c) { return (size_t)(c->G / 16) * 6 * 8; }
 
@@ -369,10 +371,18 @@ nqs_status nqs_eloc(nqs_ctx* c, const int8_t* spins, int64_t S, double* logpsi_o
     const int64_t n = std::min(wk.chunk, S - s0);
     double* lp = logpsi_out ? logpsi_out + 2 * s0 : wk.lp;
     const int8_t* sp = spins + s0 * c->N;
-    const hipError_t e =
-        fused ? NQS_RUN(c, K_ELOC, st,
-                        launch_eloc_fused(c, sp, n, wk.partial, lp, eloc_out + 2 * s0, 2, st))
-              : eloc_chunk(c, wk, sp, n, lp, eloc_out + 2 * s0, 2, st);
+    hipError_t e;
+    if (fused && eloc_fused_supported(c)) {
+      e = NQS_RUN(c, K_ELOC, st,
+                  launch_eloc_fused(c, sp, n, wk.partial, lp, eloc_out + 2 * s0, 2, st));
+    } else if (fused) {
+      e = NQS_RUN(c, K_ELOC, st, launch_eloc_wide(c, sp, n, wk.partial, st));
+      if (e == hipSuccess)
+        e = NQS_RUN(c, K_ELOC_FIN, st,
+                    launch_fused_finish(c, sp, n, wk.partial, lp, eloc_out + 2 * s0, 2, st));
+    } else {
+      e = eloc_chunk(c, wk, sp, n, lp, eloc_out + 2 * s0, 2, st);
+    }
     if (e != hipSuccess) return hip_fail(c, e, "eloc launch");
   }
   return NQS_OK;

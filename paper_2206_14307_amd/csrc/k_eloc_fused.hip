@@ -413,6 +413,15 @@ bool fits(int prec) {
 
 }  // namespace
 
+hipError_t launch_fused_finish(const nqs_ctx* c, const int8_t* spins, int64_t S,
+                               const double* part, double* logpsi, double* eloc, int eloc_stride,
+                               hipStream_t st) {
+  if (S <= 0) return hipSuccess;
+  fused_finish_kernel<<<(unsigned)S, 64, 0, st>>>(spins, c->N, c->NB, c->G / 16, c->dev.bonds,
+                                                  c->dev.bond_J, part, logpsi, eloc, eloc_stride);
+  return hipGetLastError();
+}
+
 bool eloc_fused_supported(const nqs_ctx* c) {
   const int N = c->N, K = c->K, M = c->M, p = c->prec;
   if (N == 16 && K == 1 && M == 16) return fits<16, 1, 16>(p);

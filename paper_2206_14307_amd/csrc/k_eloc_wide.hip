@@ -1,0 +1,326 @@
+// Fused log psi + E_loc (Sec. 3.1 Eqs. (2), (6); Sec. 3.2 Eq. (10)) for
+// models whose hidden layer does not fit in registers (K*M > 128,
+// M a multiple of 16), with theta in FP32 or split BF16.
+//
+// A workgroup of kWideWaves wavefronts takes one sample at a time; every
+// wavefront takes one 16-image column block, so all of them share the
+// sample's antiparallel-bond list and do the same amount of work.  The hidden
+// units are walked in chunks of kHC in lockstep across the workgroup:
+//   * the chunk's rows of the bond table T = tanh(D) (all 4N bonds x kHC units)
+//     are staged in LDS, double-buffered: each thread loads its share of the
+//     next chunk into registers at the start of a chunk and stores it at the
+//     end, so the loads overlap a whole chunk of work;
+//   * theta of the chunk (kHC/8 hidden tiles) runs on 16x16 MFMA with the W
+//     fragments read from L2, and the log 2cosh / tanh epilogue accumulates
+//     log psi of the image across chunks;
+//   * tanh(theta) of the chunk goes through a small LDS tile so that lane
+//     (qg, c) holds all kHC values of image c, and the lane multiplies the
+//     running products F_s prod_h (s + t_h T_h) of its bonds b = qg + 4 jb
+//     (jb < kWideBonds) of the list, the bond rows read from LDS.
+// At the end of each RBM the products are weighted with the image weights
+// u = chi e^{L - m} (m a running maximum over the RBMs of the wave's images)
+// and summed; the wave emits (m, sum u, sum u R) per (sample, column block)
+// in the same format as the fused kernel, combined by its finish kernel.
+// Bonds beyond 4 kWideBonds per sample are handled in further passes.
+#include "theta_common.h"
+
+namespace nqs {
+
+namespace {
+
+constexpr int kWideWaves = 8;
+constexpr int kWideBonds = 16;     // bonds per lane and pass
+constexpr int kHC = 8;             // hidden units per chunk (multiple of 8)
+constexpr int kRP = kHC / 2;       // float4 per staged row
+constexpr int kTS = 2 * kHC + 4;   // LDS row stride of the staged table (floats)
+constexpr int kXS = 2 * kHC + 4;   // LDS row stride of the tanh exchange tile (floats)
+
+template <int N>
+struct WideCfg {
+  static constexpr int NB = 4 * N;
+  static constexpr int NSTG = (NB * kRP + 64 * kWideWaves - 1) / (64 * kWideWaves);  // float4 / thread
+  static constexpr size_t LDS = 2ull * NB * kTS * 4 + (size_t)kWideWaves * 16 * kXS * 4 + NB * 2 + 16;
+};
+
+template <int N, int PREC>
+__global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
+    const int8_t* __restrict__ spins, int64_t S, const uint8_t* __restrict__ perm, int G, int K,
+    int M, const typename ThetaTraits<PREC>::AFrag* __restrict__ wfrag,
+    const float* __restrict__ bias, const float* __restrict__ avec,
+    const int32_t* __restrict__ bonds, const int32_t* __restrict__ bmap,
+    const double* __restrict__ chi, const float* __restrict__ Tpm, const float* __restrict__ F,
+    double* __restrict__ part) {
+  using T = ThetaTraits<PREC>;
+  using Cfg = WideCfg<N>;
+  constexpr int NB = Cfg::NB, NK = nk_of<N, PREC>(), NSTG = Cfg::NSTG;
+  __shared__ __align__(16) float Tc[2][NB * kTS];
+  __shared__ __align__(16) float tx[kWideWaves][16 * kXS];
+  __shared__ uint16_t list[NB];
+  __shared__ int nc_s;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int q = lane >> 4, c = lane & 15;
+  const int KM = K * M, NCH = KM / kHC, CPR = M / kHC, nblk = G / 16;
+  const int rounds = (nblk + kWideWaves - 1) / kWideWaves;
+
+  // staging of chunk ch: element e = tid + 512 i -> row e / kRP, 16-byte part
+  // e % kRP of tanh(D); thread tid < NB also stages (F_+, F_-) of row tid for
+  // the chunk's RBM into the row's last 16 bytes.  The values sit in named
+  // registers (s0..s7, sF) between the loads and the LDS stores; the loads are
+  // unconditional (clamped to valid elements).
+  static_assert(NSTG <= 8, "staging registers");
+  float4 s0, s1, s2, s3, s4, s5, s6, s7, sF;
+#define NQS_STG_LD(I, CH)                                                                \
+  if constexpr (I < NSTG) {                                                              \
+    int e = tid + 64 * kWideWaves * I;                                                   \
+    e = e < NB * kRP ? e : 0;                                                            \
+    s##I = *reinterpret_cast<const float4*>(Tpm + (size_t)(e / kRP) * 4 * KM +           \
+                                            2 * kHC * (CH) + 4 * (e % kRP));             \
+  }
+#define NQS_STG_ST(I, BUF)                                                               \
+  if constexpr (I < NSTG) {                                                              \
+    const int e = tid + 64 * kWideWaves * I;                                             \
+    if (e < NB * kRP) *reinterpret_cast<float4*>(&Tc[BUF][(e / kRP) * kTS + 4 * (e % kRP)]) = s##I; \
+  }
+#define NQS_STAGE_LOAD(CH)                                                               \
+  {                                                                                      \
+    NQS_STG_LD(0, CH) NQS_STG_LD(1, CH) NQS_STG_LD(2, CH) NQS_STG_LD(3, CH)              \
+    NQS_STG_LD(4, CH) NQS_STG_LD(5, CH) NQS_STG_LD(6, CH) NQS_STG_LD(7, CH)              \
+    sF = *reinterpret_cast<const float4*>(F + ((size_t)((CH) / CPR) * NB + (tid < NB ? tid : 0)) * 4); \
+  }
+#define NQS_STAGE_STORE(BUF)                                                             \
+  {                                                                                      \
+    NQS_STG_ST(0, BUF) NQS_STG_ST(1, BUF) NQS_STG_ST(2, BUF) NQS_STG_ST(3, BUF)          \
+    NQS_STG_ST(4, BUF) NQS_STG_ST(5, BUF) NQS_STG_ST(6, BUF) NQS_STG_ST(7, BUF)          \
+    if (tid < NB) *reinterpret_cast<float4*>(&Tc[BUF][tid * kTS + 2 * kHC]) = sF;        \
+  }
+  NQS_STAGE_LOAD(0)
+  NQS_STAGE_STORE(0)
+  int gc = 0;                                  // chunks processed by the workgroup so far
+
+  for (int64_t s = blockIdx.x; s < S; s += gridDim.x) {
+    const int8_t* srow = spins + s * N;
+    __syncthreads();                           // previous sample done with the list
+    if (wv == 0) {
+      int n = 0;
+      for (int base = 0; base < NB; base += 64) {
+        const int b = base + lane;
+        bool anti = false;
+        int sp = 0;
+        if (b < NB) {
+          sp = srow[bonds[2 * b]];
+          anti = sp != srow[bonds[2 * b + 1]];
+        }
+        const unsigned long long msk = __ballot(anti);
+        const int pos = __popcll(msk & ((1ull << lane) - 1ull));
+        if (anti) list[n + pos] = (uint16_t)(b | (sp > 0 ? 0x8000 : 0));
+        n += __popcll(msk);
+      }
+      if (lane == 0) nc_s = n;
+    }
+    __syncthreads();
+    const int nc = nc_s;
+    const int npass = nc > 0 ? (nc + 4 * kWideBonds - 1) / (4 * kWideBonds) : 1;
+
+    for (int rd = 0; rd < rounds; ++rd) {
+      const int blk = rd * kWideWaves + wv;
+      const bool active = blk < nblk;
+      const int g = (active ? blk : 0) * 16 + c;
+      const uint8_t* prow = perm + (size_t)g * N;
+      typename T::BFrag bx[NK];
+      load_bfrag<N, PREC>(srow, prow, q, bx);
+      const float ch_g = (float)chi[g];
+      double m_item = -INFINITY, Qr = 0.0, Qi = 0.0, denr = 0.0, deni = 0.0;
+
+      for (int pass = 0; pass < npass; ++pass) {
+        // this lane's bonds: list entries pass * 4 kWideBonds + q + 4 jb
+        int offs[kWideBonds];                  // 2 * (row offset in floats) + (sign < 0)
+        const int i0 = pass * 4 * kWideBonds + q;
+        const int nv = nc > i0 ? min(kWideBonds, (nc - i0 + 3) / 4) : 0;
+#pragma unroll
+        for (int jb = 0; jb < kWideBonds; ++jb) {
+          const int ii = i0 + 4 * jb;
+          const int e = ii < nc ? list[ii] : 0;   // padding entries use bond 0
+          const int v = bmap[(size_t)g * NB + (e & 0x7fff)];
+          offs[jb] = 2 * ((v >> 1) * kTS) + ((e >> 15) ^ (v & 1));
+        }
+        float Pr[kWideBonds], Pi[kWideBonds];
+        float lpr = 1.f, lpi = 0.f;
+        int lpe = 0;
+        double sax = 0.0;
+
+        for (int ch = 0; ch < NCH; ++ch, ++gc) {
+          const int k = ch / CPR;
+          const int buf = gc & 1;
+          const int nxt = ch + 1 < NCH ? ch + 1 : 0;
+          if (ch % CPR == 0) {                 // RBM start: products begin at F_s
+#pragma unroll
+            for (int jb = 0; jb < kWideBonds; ++jb) {
+              const float* f = Tc[buf] + (offs[jb] >> 1) + 2 * kHC + 2 * (offs[jb] & 1);
+              Pr[jb] = f[0];
+              Pi[jb] = f[1];
+            }
+          }
+          // theta of the chunk's hidden tiles, epilogue, tanh to LDS
+#pragma unroll
+          for (int tt = 0; tt < kHC / 8; ++tt) {
+            const int ht = (kHC / 8) * ch + tt;
+            typename T::Acc acc = typename T::Acc{0, 0, 0, 0};
+#pragma unroll
+            for (int kk = 0; kk < NK; ++kk) acc = mfma(wfrag[((size_t)ht * NK + kk) * 64 + lane], bx[kk], acc);
+            const int h0 = 8 * ht + 2 * q;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              const float x = acc[2 * u] + bias[2 * (h0 + u)];
+              const float y = acc[2 * u + 1] + bias[2 * (h0 + u) + 1];
+              float tr, ti;
+              logcosh_step<float, true>(x, y, lpr, lpi, sax, tr, ti);
+              const int hl = 8 * tt + 2 * q + u;
+              tx[wv][c * kXS + 2 * hl] = tr;
+              tx[wv][c * kXS + 2 * hl + 1] = ti;
+            }
+          }
+          renorm(lpr, lpi, lpe);
+          wave_sync_lds();
+          float t[2 * kHC];
+#pragma unroll
+          for (int e = 0; e < kHC / 2; ++e) {
+            const float4 v = *reinterpret_cast<const float4*>(&tx[wv][c * kXS + 4 * e]);
+            t[4 * e] = v.x; t[4 * e + 1] = v.y; t[4 * e + 2] = v.z; t[4 * e + 3] = v.w;
+          }
+          NQS_STAGE_LOAD(nxt)                  // lands during the bond products
+          // bond products of the chunk, two bonds at a time
+#pragma unroll
+          for (int jb = 0; jb < kWideBonds; jb += 2) {
+            const float* r0 = Tc[buf] + (offs[jb] >> 1);
+            const float* r1 = Tc[buf] + (offs[jb + 1] >> 1);
+            const float sg0 = (offs[jb] & 1) ? -1.f : 1.f, sg1 = (offs[jb + 1] & 1) ? -1.f : 1.f;
+            float ar = Pr[jb], ai = Pi[jb], br = Pr[jb + 1], bi = Pi[jb + 1];
+#pragma unroll
+            for (int e = 0; e < kHC / 2; ++e) {
+              const float4 x0 = *reinterpret_cast<const float4*>(r0 + 4 * e);
+              const float4 x1 = *reinterpret_cast<const float4*>(r1 + 4 * e);
+#pragma unroll
+              for (int hh = 0; hh < 2; ++hh) {
+                const float tr = t[4 * e + 2 * hh], ti = t[4 * e + 2 * hh + 1];
+                const float T0r = hh ? x0.z : x0.x, T0i = hh ? x0.w : x0.y;
+                const float T1r = hh ? x1.z : x1.x, T1i = hh ? x1.w : x1.y;
+                float pa = fmaf(tr, T0r, fmaf(-ti, T0i, sg0)), pb = fmaf(tr, T0i, ti * T0r);
+                float nr = fmaf(ar, pa, -(ai * pb));
+                ai = fmaf(ar, pb, ai * pa);
+                ar = nr;
+                pa = fmaf(tr, T1r, fmaf(-ti, T1i, sg1));
+                pb = fmaf(tr, T1i, ti * T1r);
+                nr = fmaf(br, pa, -(bi * pb));
+                bi = fmaf(br, pb, bi * pa);
+                br = nr;
+              }
+            }
+            Pr[jb] = ar; Pi[jb] = ai; Pr[jb + 1] = br; Pi[jb + 1] = bi;
+          }
+          if (ch % CPR == CPR - 1) {           // RBM k complete: weight and sum
+            int E = lpe;
+            float pr = lpr, pi = lpi;
+            double sx = sax;
+#pragma unroll
+            for (int o = 16; o <= 32; o <<= 1) {
+              const float orr = __shfl_xor(pr, o, 64), oi = __shfl_xor(pi, o, 64);
+              const float nr = pr * orr - pi * oi;
+              pi = pr * oi + pi * orr;
+              pr = nr;
+              E += __shfl_xor(E, o, 64);
+              sx += __shfl_xor(sx, o, 64);
+            }
+            double axr = 0.0, axi = 0.0;
+            const float* ak = avec + (size_t)k * N * 2;
+            for (int jj = q; jj < N; jj += 4) {
+              const double xj = 0.5 * (double)srow[prow[jj]];
+              axr += xj * (double)ak[2 * jj];
+              axi += xj * (double)ak[2 * jj + 1];
+            }
+            axr += __shfl_xor(axr, 16, 64);
+            axi += __shfl_xor(axi, 16, 64);
+            axr += __shfl_xor(axr, 32, 64);
+            axi += __shfl_xor(axi, 32, 64);
+            const double Er = axr + sx + (double)E * 0.69314718055994530942;
+            const double mk = wave_max(Er);
+            if (mk > m_item) {
+              const double sc = (double)exp_t((float)(m_item - mk));   // 0 at the first RBM
+              Qr *= sc; Qi *= sc; denr *= sc; deni *= sc;
+              m_item = mk;
+            }
+            const float e = ch_g * exp_t((float)(Er - m_item));
+            float sn, cs;
+            sincos_t((float)axi, &sn, &cs);
+            const float ur = e * (pr * cs - pi * sn), ui = e * (pr * sn + pi * cs);
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int jb = 0; jb < kWideBonds; ++jb) {
+              sr += jb < nv ? (double)Pr[jb] : 0.0;
+              si += jb < nv ? (double)Pi[jb] : 0.0;
+            }
+            Qr += (double)ur * sr - (double)ui * si;
+            Qi += (double)ur * si + (double)ui * sr;
+            if (pass == 0 && q == 0) {
+              denr += (double)ur;
+              deni += (double)ui;
+            }
+            lpr = 1.f; lpi = 0.f; lpe = 0; sax = 0.0;
+          }
+          NQS_STAGE_STORE(gc & 1 ? 0 : 1)
+          __syncthreads();
+        }
+      }
+      Qr = wave_sum(Qr);
+      Qi = wave_sum(Qi);
+      denr = wave_sum(denr);
+      deni = wave_sum(deni);
+      if (active && lane == 0) {
+        double* o = part + ((size_t)s * nblk + blk) * 6;
+        o[0] = m_item;
+        o[1] = denr;
+        o[2] = deni;
+        o[3] = Qr;
+        o[4] = Qi;
+        o[5] = 0.0;
+      }
+    }
+  }
+}
+
+#undef NQS_STG_LD
+#undef NQS_STG_ST
+#undef NQS_STAGE_LOAD
+#undef NQS_STAGE_STORE
+
+template <int N, int PREC>
+hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>(S, c->n_cu > 0 ? c->n_cu : 256);
+  eloc_wide_kernel<N, PREC><<<(unsigned)blocks, 64 * kWideWaves, 0, st>>>(
+      spins, S, c->dev.perm, c->G, c->K, c->M,
+      (const typename ThetaTraits<PREC>::AFrag*)c->par.wfrag, (const float*)c->par.bias,
+      (const float*)c->par.avec, c->dev.bonds, c->dev.bmap, c->dev.chi, (const float*)c->par.Tpm,
+      (const float*)c->par.F, part);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool eloc_wide_supported(const nqs_ctx* c) {
+  if (c->prec == NQS_FP64 || c->KM <= 128 || c->M % kHC != 0) return false;
+  return c->N == 36 || c->N == 64 || c->N == 100;
+}
+
+hipError_t launch_eloc_wide(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part,
+                            hipStream_t st) {
+  if (S <= 0) return hipSuccess;
+  const bool bf = c->prec == NQS_BF16X2;
+  switch (c->N) {
+    case 36: return bf ? run<36, NQS_BF16X2>(c, spins, S, part, st) : run<36, NQS_FP32>(c, spins, S, part, st);
+    case 64: return bf ? run<64, NQS_BF16X2>(c, spins, S, part, st) : run<64, NQS_FP32>(c, spins, S, part, st);
+    case 100: return bf ? run<100, NQS_BF16X2>(c, spins, S, part, st) : run<100, NQS_FP32>(c, spins, S, part, st);
+    default: return hipErrorNotSupported;
+  }
+}
+
+}  // namespace nqs

@@ -140,6 +140,12 @@ hipError_t launch_eloc_bonds_reg(const nqs_ctx* c, const int8_t* spins, int64_t 
 // variants); part holds S * (G/16) * 6 doubles.
 bool eloc_fused_supported(const nqs_ctx* c);
 bool grad_fused_supported(const nqs_ctx* c);
+bool eloc_wide_supported(const nqs_ctx* c);
+hipError_t launch_eloc_wide(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part,
+                            hipStream_t st);
+hipError_t launch_fused_finish(const nqs_ctx* c, const int8_t* spins, int64_t S,
+                               const double* part, double* logpsi, double* eloc, int eloc_stride,
+                               hipStream_t st);
 hipError_t launch_grad_fused(const nqs_ctx* c, const int8_t* spins, int64_t S, void* O,
                              double* logpsi, hipStream_t st);
 hipError_t launch_eloc_fused(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part,

@@ -278,3 +278,37 @@ def test_eloc_both_factor_forms(name, case):
     tol = TOL[w.precision]
     assert max_logpsi_err(glp.cpu().numpy(), oracle.logpsi(om, p, sp)) < tol
     assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp)) < tol
+
+
+# ----------------------------------------------- wide hidden layers (K*M > 128)
+
+def _neel_and_stripe(L):
+    x, y = np.meshgrid(np.arange(L), np.arange(L), indexing="xy")
+    neel = np.where((x + y) % 2 == 0, 1, -1).astype(np.int8).reshape(-1)
+    stripe = np.where(x % 2 == 0, 1, -1).astype(np.int8).reshape(-1)
+    return np.stack([neel, stripe])
+
+
+@pytest.mark.parametrize("name,over,std", [
+    ("8x8_k4_m256", {"precision": "fp32"}, None),
+    ("10x10_m400", {}, None),
+    ("6x6_fp32_eloc", {"n_hidden": 144, "irrep": "B1", "kx": 3, "ky": 3}, 0.1),
+])
+def test_wide_models_many_samples_and_bond_passes(name, over, std):
+    """Models with K*M > 128 take the wide kernel: one workgroup per sample,
+    hidden units in chunks, 16 bonds per lane and pass.  300 configurations
+    (more than one per workgroup) with the Neel and stripe states first (2N and
+    3N antiparallel bonds: several bond passes); rows checked one by one."""
+    w = dataclasses.replace(WORKLOADS[name], **over)
+    p = draw_params(w) if std is None else stress_params(w, std, 31)
+    om = oracle.Model.from_workload(w)
+    sp = np.concatenate([_neel_and_stripe(w.L), random_sz0_spins(w.N, 298, 12)])
+    m = make(w, p)
+    glp, gel = m.eloc(cuda(sp))
+    rows = np.r_[0, 1, 299]                  # Neel, stripe, a later sample of a workgroup
+    sub = sp[rows]
+    keep = nonzero_rows(om, p, sub)
+    rows, sub = rows[keep], sub[keep]
+    tol = TOL[w.precision]
+    assert max_logpsi_err(glp.cpu().numpy()[rows], oracle.logpsi(om, p, sub)) < tol
+    assert max_rel_err(gel.cpu().numpy()[rows], oracle.eloc_direct(om, p, sub)) < tol
