@@ -259,10 +259,14 @@ def leg_precision(name, steps=2):
     return out
 
 
-def leg_sr(name="10x10_m400", S=8192, steps=1):
-    """logpsi + E_loc + O_k for S configurations, then the sample-space SR step."""
+def leg_sr(name="10x10_m400", S=32768, steps=1):
+    """logpsi + E_loc + O_k for S configurations (the 10x10 workload's sample
+    count), then the sample-space SR step; the Gram matrix and the Cholesky
+    factorisation + solves are timed with the library's HIP events."""
+    import ctypes as C
     import torch
     from paper_2206_14307_amd import NQS
+    from paper_2206_14307_amd.nqs import KERNELS
     from workloads import WORKLOADS, draw_params, random_sz0_spins_fast
     w = WORKLOADS[name]
     m = NQS.from_workload(w)
@@ -272,13 +276,27 @@ def leg_sr(name="10x10_m400", S=8192, steps=1):
     holder = {}
     ms_e = timed(lambda: holder.update(e=m.eloc(sp, want_logpsi=False)), steps, 0)
     ms_g = timed(lambda: holder.update(O=m.grad(sp)), steps, 0)
+    m.profile(True)
     ms_sr = timed(lambda: holder.update(d=m.sr_solve(holder["O"], holder["e"], 1e-6, 0.01)),
                   steps, 0)
+    part = {}
+    for k in ("gram", "cholesky"):
+        ms, n = C.c_double(0), C.c_int64(0)
+        m.lib.nqs_profile_read(m._ctx, KERNELS[k], C.byref(ms), C.byref(n), 1)
+        part[k] = ms.value / max(n.value, 1)
+    m.profile(False)
     flops_gram = 8.0 * S * S * m.P / 2
+    flops_chol = 8.0 * S ** 3 / 3
+    pk_gram = 78.6 if w.precision == "fp64" else 157.3
     return {"workload": name, "S": S, "P": m.P, "precision": w.precision,
             "ms_eloc": ms_e, "ms_grad": ms_g, "ms_sr": ms_sr,
-            "gram_flops_lower_half": flops_gram,
-            "cholesky_flops": 8.0 * S ** 3 / 3,
+            "gram": {"ms": part["gram"], "flops_lower_half": flops_gram, "bound": "mfma",
+                     "achieved": flops_gram / part["gram"] / 1e9, "peak": pk_gram,
+                     "unit": "TFLOP/s", "frac": flops_gram / part["gram"] / 1e9 / pk_gram},
+            "cholesky_and_solves": {"ms": part["cholesky"], "flops": flops_chol, "bound": "mfma",
+                                    "achieved": flops_chol / part["cholesky"] / 1e9,
+                                    "peak": 78.6, "unit": "TFLOP/s",
+                                    "frac": flops_chol / part["cholesky"] / 1e9 / 78.6},
             "dtheta_norm": float(holder["d"].abs().pow(2).sum().sqrt().item())}
 
 

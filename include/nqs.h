@@ -150,6 +150,17 @@ nqs_status nqs_sr_solve(nqs_ctx* ctx, const void* O, const double* eloc, int64_t
                         double dtau, double* dtheta_out, void* ws, size_t ws_bytes,
                         hipStream_t stream);
 
+/* The Sz = 0 sector, i.e. all configurations with N/2 up spins (the exact
+ * evaluations of Sec. 3.3 run over it on the 4x4 lattice), in colex order of
+ * the up-site sets = increasing bit mask sum_{i up} 2^i: row r of
+ * spins_out [count][N] int8 (+1 up, -1 down) is the r-th configuration.
+ * count (host pointer, required) receives C(N, N/2).  With spins_out = NULL
+ * only the count is returned.  NQS_ERR_ARG if cap < count, or if the sector
+ * has more than 2^31 configurations (L >= 6; the count is still returned
+ * when it fits in int64, i.e. up to L = 8).  Asynchronous on the stream. */
+nqs_status nqs_enumerate_sz0(nqs_ctx* ctx, int8_t* spins_out, int64_t cap, int64_t* count,
+                             hipStream_t stream);
+
 /* Pack initial configurations into chain states: chain_state [n][4] uint64
  * = {spin bits 0..63, spin bits 64..127, proposal counter = 0, chain id}
  * with chain ids first_chain_id + c.  spins: [n][N] int8 (Sz = 0). */
@@ -179,7 +190,9 @@ nqs_status nqs_sample(nqs_ctx* ctx, int64_t n_chains, int64_t n_per_chain, int32
  * this context is bracketed by HIP events on the call's stream.
  * nqs_profile_read synchronises those events and returns, for kernel id
  * `kernel` (0 theta, 1 lse, 2 eloc_bonds, 3 eloc_finish, 4 twohop,
- * 5 twohop_finish, 6 moments, 7 grad, 8 sample, 9 sr), the summed duration
+ * 5 twohop_finish, 6 moments, 7 grad, 8 sample, 9 sr (whole nqs_sr_solve),
+ * 10 gram (the S x S Gram matrix of nqs_sr_solve), 11 cholesky (its blocked
+ * factorisation and the two triangular solves)), the summed duration
  * in ms and the launch count since the last reset; reset = 1 clears them. */
 nqs_status nqs_profile_enable(nqs_ctx* ctx, int on);
 nqs_status nqs_profile_read(nqs_ctx* ctx, int kernel, double* ms_out, int64_t* launches_out,

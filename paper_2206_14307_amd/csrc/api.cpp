@@ -168,7 +168,7 @@ hipError_t prep_tables(nqs_ctx* c, hipStream_t st) {
 
 void free_all(nqs_ctx* c) {
   void* ptrs[] = {c->dev.perm, c->dev.perminv, c->dev.bonds, c->dev.bond_J, c->dev.bmap, c->dev.chi,
-                  c->dev.fmap, c->dev.frow,
+                  c->dev.fmap, c->dev.frow, c->dev.binom,
                   c->par.params, c->par.wfrag, c->par.bias, c->par.avec, c->par.Tpm,
                   c->par.F, c->par.Tpair, c->par.Fpair, c->par.Tdir, c->par.Urec, c->par.flag};
   for (void* p : ptrs)
@@ -252,6 +252,14 @@ nqs_status nqs_create(const nqs_model_desc* d, nqs_ctx** out) {
   if (st == NQS_OK) st = upload(c, &c->dev.bond_J, c->geo.bond_J);
   if (st == NQS_OK) st = upload(c, &c->dev.bmap, c->geo.bmap);
   if (st == NQS_OK) st = upload(c, &c->dev.chi, c->geo.chi);
+  {
+    std::vector<uint64_t> binom;
+    if (nqs::sz0_binomials(c->N, binom, c->sector_count)) {
+      if (st == NQS_OK) st = upload(c, &c->dev.binom, binom);
+    } else {
+      c->sector_count = -1;
+    }
+  }
   if (st == NQS_OK && eloc_fused_supported(c)) {
     // bank-conflict-free LDS rows for the fused kernel, else plain odd-stride rows
     const int rb = c->prec == NQS_FP64 ? 8 : 4;
@@ -460,6 +468,22 @@ nqs_status nqs_grad(nqs_ctx* c, const int8_t* spins, int64_t S, void* O_out, dou
     if (e != hipSuccess) return hip_fail(c, e, "grad launch");
   }
   return NQS_OK;
+}
+
+nqs_status nqs_enumerate_sz0(nqs_ctx* c, int8_t* spins_out, int64_t cap, int64_t* count,
+                             hipStream_t st) {
+  if (!c) return NQS_ERR_ARG;
+  if (!count) return fail(c, NQS_ERR_ARG, "enumerate_sz0: count is NULL");
+  if (c->sector_count < 0) return fail(c, NQS_ERR_ARG, "enumerate_sz0: sector size overflows int64");
+  *count = c->sector_count;
+  if (!spins_out) return NQS_OK;
+  if (c->sector_count > (int64_t)1 << 31)
+    return fail(c, NQS_ERR_ARG, "enumerate_sz0: more than 2^31 configurations");
+  if (cap < c->sector_count)
+    return fail(c, NQS_ERR_ARG, "enumerate_sz0: cap " + std::to_string(cap) + " < " +
+                                    std::to_string(c->sector_count));
+  const hipError_t e = launch_enum_sz0(c, c->sector_count, spins_out, st);
+  return e == hipSuccess ? NQS_OK : hip_fail(c, e, "enumerate_sz0 launch");
 }
 
 nqs_status nqs_profile_enable(nqs_ctx* c, int on) {

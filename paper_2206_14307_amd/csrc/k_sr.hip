@@ -446,8 +446,11 @@ hipError_t sr_run(const nqs_ctx* c, const void* Ov, const double* el, int64_t S,
                                                Tre, Tim);
   eps_kernel<<<1, 1024, 0, st>>>(el, S, S32, v);
   const int64_t ntri = nblk * (nblk + 1) / 2;
+  prof_begin(c, K_GRAM, st);
   gram_kernel<RG><<<(unsigned)((ntri + 3) / 4), 256, 0, st>>>(Tre, Tim, P4, S32, nblk, lambda, T);
+  prof_end(c, K_GRAM, st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  prof_begin(c, K_CHOL, st);
   for (int64_t k = 0; k < nblk; ++k) {
     potrf_diag_kernel<<<1, 256, 0, st>>>(T, S32, k, flag);
     const int64_t rows = S32 - (k + 1) * kB;
@@ -467,6 +470,7 @@ hipError_t sr_run(const nqs_ctx* c, const void* Ov, const double* el, int64_t S,
     bsolve_diag_kernel<<<1, 64, 0, st>>>(T, S32, k, v);
     if (k > 0) bsolve_update_kernel<<<(unsigned)((k * kB + 255) / 256), 256, 0, st>>>(T, S32, k, v);
   }
+  prof_end(c, K_CHOL, st);
   dtheta_kernel<RG><<<(unsigned)((P + 3) / 4), 256, 0, st>>>(Tre, Tim, P, S32, v, dtau, out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(flag_host, flag, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)

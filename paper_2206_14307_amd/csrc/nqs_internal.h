@@ -40,6 +40,9 @@ constexpr int fused_row16(int K, int M, int real_bytes) {
 constexpr int fused_cap16(int NB, int row16) { return NB * (row16 | 1) + 256; }
 std::vector<int> place_fused_rows(const Geometry& geo, int row16, int cap16);
 
+// Binomial table of the Sz = 0 enumeration; false if C(N, N/2) overflows int64.
+bool sz0_binomials(int N, std::vector<uint64_t>& b, int64_t& count);
+
 // Device-side tables owned by the context.
 struct DeviceTables {
   uint8_t* perm = nullptr;        // [G][N]
@@ -48,6 +51,7 @@ struct DeviceTables {
   double* bond_J = nullptr;       // [NB]
   int32_t* bmap = nullptr;        // [G][NB]
   double* chi = nullptr;          // [G]
+  uint64_t* binom = nullptr;      // [N+1][N+1] binomials (Sz = 0 enumeration), if C(N,N/2) fits
   int32_t* fmap = nullptr;        // [G][NB] fused kernel: 2 * (LDS row offset in reals) + flip
   int32_t* frow = nullptr;        // [NB]    fused kernel: LDS row offset in reals
 };
@@ -73,7 +77,7 @@ struct ParamTables {
 
 namespace nqs {
 enum KernelId { K_THETA = 0, K_LSE, K_ELOC, K_ELOC_FIN, K_TWOHOP, K_TWOHOP_FIN, K_MOMENTS,
-                K_GRAD, K_SAMPLE, K_SR, K_COUNT };
+                K_GRAD, K_SAMPLE, K_SR, K_GRAM, K_CHOL, K_COUNT };
 struct Profiler {
   bool on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[K_COUNT];
@@ -87,6 +91,7 @@ struct nqs_ctx {
   int L = 0, N = 0, G = 0, NB = 0, K = 0, M = 0, KM = 0, P_rbm = 0;
   int64_t P = 0;
   int prec = 1;
+  int64_t sector_count = -1;      // C(N, N/2), -1 if it overflows int64
   int n_htiles = 0;               // K*M/8 hidden tiles of 8 units (16 interleaved rows)
   int nk = 0;                     // MFMA K-steps over the site axis
   nqs::Geometry geo;
@@ -95,12 +100,12 @@ struct nqs_ctx {
   std::string last_error;
   int device = 0;
   int n_cu = 0;                   // compute units of the device (persistent grids)
-  nqs::Profiler prof;
+  mutable nqs::Profiler prof;   // timing only, not model state
 };
 
 namespace nqs {
 // Bracket one launch with events when profiling is enabled.
-inline void prof_begin(nqs_ctx* c, int k, hipStream_t st) {
+inline void prof_begin(const nqs_ctx* c, int k, hipStream_t st) {
   if (!c->prof.on) return;
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess) return;
@@ -108,7 +113,7 @@ inline void prof_begin(nqs_ctx* c, int k, hipStream_t st) {
   (void)hipEventRecord(a, st);
   c->prof.ev[k].push_back({a, b});
 }
-inline void prof_end(nqs_ctx* c, int k, hipStream_t st) {
+inline void prof_end(const nqs_ctx* c, int k, hipStream_t st) {
   if (!c->prof.on || c->prof.ev[k].empty()) return;
   (void)hipEventRecord(c->prof.ev[k].back().second, st);
 }
@@ -140,6 +145,7 @@ hipError_t launch_eloc_bonds_reg(const nqs_ctx* c, const int8_t* spins, int64_t 
 // variants); part holds S * (G/16) * 6 doubles.
 bool eloc_fused_supported(const nqs_ctx* c);
 bool grad_fused_supported(const nqs_ctx* c);
+hipError_t launch_enum_sz0(const nqs_ctx* c, int64_t count, int8_t* out, hipStream_t st);
 bool eloc_wide_supported(const nqs_ctx* c);
 hipError_t launch_eloc_wide(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part,
                             hipStream_t st);

@@ -312,3 +312,34 @@ def test_wide_models_many_samples_and_bond_passes(name, over, std):
     tol = TOL[w.precision]
     assert max_logpsi_err(glp.cpu().numpy()[rows], oracle.logpsi(om, p, sub)) < tol
     assert max_rel_err(gel.cpu().numpy()[rows], oracle.eloc_direct(om, p, sub)) < tol
+
+
+# ------------------------------------------------------------ Sz = 0 sector
+
+def test_enumerate_sz0_matches_oracle_basis(sector16):
+    """nqs_enumerate_sz0 is integer work: bit-exact against the oracle's
+    increasing-mask (colex) basis of the 4x4 sector."""
+    from paper_2206_14307_amd import NQS
+    m = NQS.from_workload(WORKLOADS["4x4_fp64_exact"])
+    assert m.sector_size() == 12870
+    got = m.enumerate_sz0().cpu().numpy()
+    assert np.array_equal(got, sector16[1])
+
+
+def test_enumerate_sz0_limits():
+    import ctypes as C
+    from paper_2206_14307_amd import NQS, NQSError
+    from paper_2206_14307_amd.nqs import _stream
+    m4 = NQS.from_workload(WORKLOADS["4x4_fp64_exact"])
+    buf = torch.empty((100, 16), dtype=torch.int8, device="cuda")
+    n = C.c_int64(0)
+    st = m4.lib.nqs_enumerate_sz0(m4._ctx, C.c_void_p(buf.data_ptr()), 100, C.byref(n), _stream())
+    assert st == 1 and n.value == 12870                  # cap too small: NQS_ERR_ARG
+    m6 = NQS.from_workload(WORKLOADS["6x6_fp32_eloc"])
+    assert m6.sector_size() == 9075135300                # counted, too large to enumerate
+    st = m6.lib.nqs_enumerate_sz0(m6._ctx, C.c_void_p(buf.data_ptr()), 1 << 40, C.byref(n),
+                                  _stream())
+    assert st == 1 and n.value == 9075135300
+    m10 = NQS.from_workload(WORKLOADS["10x10_m400"])
+    with pytest.raises(NQSError):                        # C(100, 50) overflows int64
+        m10.sector_size()
