@@ -14,9 +14,11 @@ Printed as ONE JSON line, with
                   launch on the call's stream;
   cpu_baseline -- the FP64 oracle timed on this host's cores on a bounded
                   sample of the same configurations;
-  errors       -- log psi / E_loc errors of the timed path vs the oracle;
-  legs         -- the other rows of the hot path (backward, two-hop Lanczos
-                  moments, split-BF16 vs FP32 at 8x8, sampling, SR), timed.
+  errors       -- log psi / E_loc errors of the GPU path vs the oracle on the
+                  CPU-baseline sample (the only leg that runs the oracle);
+  legs         -- the other rows of the hot path (sampling, backward, log psi
+                  alone, two-hop Lanczos moments, split-BF16 vs FP32 at 8x8,
+                  SR at 10x10), timed, each with its roofline where one binds.
 """
 from __future__ import annotations
 
@@ -133,8 +135,12 @@ def _oracle_chunk(args):
     return lp, el
 
 
-def cpu_baseline(name, params, spins, budget_s=20.0):
-    """Time the oracle's log psi + E_loc on a bounded sample on all host cores."""
+def cpu_baseline(name, params, spins, budget_s=20.0, extra=()):
+    """Time the oracle's log psi + E_loc on a bounded sample on all host cores.
+    Returns the baseline record and the oracle's outputs: for the timed sample
+    (indices into spins, log psi, E_loc) and for each (name, params, spins) of
+    `extra` (evaluated in the same pool), so the GPU path's errors can be
+    stated against the oracle on the same configurations."""
     from workloads import WORKLOADS
     w = WORKLOADS[name]
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -148,16 +154,50 @@ def cpu_baseline(name, params, spins, budget_s=20.0):
     n = max(cores, (n // cores) * cores)
     log(f"cpu baseline: {per * 1e3:.1f} ms per configuration on one core; "
         f"timing {n} configurations on {cores} worker processes")
-    chunks = [(name, params, spins[i::cores][: n // cores]) for i in range(cores)]
+    idx = [np.arange(len(spins))[i::cores][: n // cores] for i in range(cores)]
+    chunks = [(name, params, spins[ix]) for ix in idx]
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
         outs = pool.map(_oracle_chunk, chunks)
     dt = time.perf_counter() - t0
-    return {"value": n * w.n_rbm * w.G / dt, "unit": "configs*sym-images/s", "cores": cores,
-            "kind": "oracle", "cpu": cpu_model(),
-            "sample": f"{n} of the benchmark's configurations, FP64 NumPy log psi + E_loc by "
-                      f"direct re-evaluation, {cores} worker processes, {dt:.1f} s"}
+    refs = {"idx": np.concatenate(idx), "logpsi": np.concatenate([o[0] for o in outs]),
+            "eloc": np.concatenate([o[1] for o in outs]), "extra": []}
+    if extra:
+        tasks = [(n_, p_, sp_[i:i + 1]) for (n_, p_, sp_) in extra for i in range(len(sp_))]
+        with ctx.Pool(min(cores, len(tasks))) as pool:
+            res = pool.map(_oracle_chunk, tasks)
+        k = 0
+        for (_, _, sp_) in extra:
+            part = res[k:k + len(sp_)]
+            k += len(sp_)
+            refs["extra"].append((np.concatenate([r[0] for r in part]),
+                                  np.concatenate([r[1] for r in part])))
+    return ({"value": n * w.n_rbm * w.G / dt, "unit": "configs*sym-images/s", "cores": cores,
+             "kind": "oracle", "cpu": cpu_model(),
+             "sample": f"{n} Sz = 0 configurations of the benchmark's size, FP64 NumPy log psi + "
+                       f"E_loc by direct re-evaluation, {cores} worker processes, {dt:.1f} s"},
+            refs)
+
+
+def errors_of(lp_gpu, el_gpu, lp_ref, el_ref):
+    """log psi / E_loc errors of GPU outputs against oracle outputs (same rows)."""
+    d = lp_gpu - lp_ref
+    d = d.real + 1j * np.angle(np.exp(1j * d.imag))
+    return {"checked": int(len(lp_ref)),
+            "max_abs_dlogpsi": float(np.abs(d).max()),
+            "max_rel_deloc": float((np.abs(el_gpu - el_ref) / np.maximum(1, np.abs(el_ref))).max()),
+            "rel_err_mean_eloc": float(abs(el_gpu.mean() - el_ref.mean()) / abs(el_ref.mean()))}
+
+
+def square_bonds(L):
+    """The 4N bonds of the L x L torus: (i, i+x), (i, i+y) (J1), (i, i+x+y), (i, i+x-y) (J2)."""
+    out = []
+    for dx, dy in ((1, 0), (0, 1), (1, 1), (1, -1)):
+        for i in range(L * L):
+            x, y = i % L, i // L
+            out.append((i, (x + dx) % L + L * ((y + dy) % L)))
+    return np.array(out, dtype=np.int64)
 
 
 # ------------------------------------------------------------------- GPU legs
@@ -176,21 +216,6 @@ def timed(fn, steps, warmup):
     return ev0.elapsed_time(ev1) / steps
 
 
-def errors_vs_oracle(name, params, spins_np, lp_gpu, el_gpu, n=12):
-    import oracle
-    from workloads import WORKLOADS
-    om = oracle.Model.from_workload(WORKLOADS[name])
-    idx = np.random.default_rng(0).choice(len(spins_np), n, replace=False)
-    lp = oracle.logpsi(om, params, spins_np[idx])
-    el = oracle.eloc_direct(om, params, spins_np[idx])
-    d = lp_gpu[idx] - lp
-    d = d.real + 1j * np.angle(np.exp(1j * d.imag))
-    return {"checked": int(n),
-            "max_abs_dlogpsi": float(np.abs(d).max()),
-            "max_rel_deloc": float((np.abs(el_gpu[idx] - el) / np.maximum(1, np.abs(el))).max()),
-            "rel_err_mean_eloc": float(abs(el_gpu[idx].mean() - el.mean()) / abs(el.mean()))}
-
-
 def leg_lanczos(steps=2):
     """Two-hop e2 + FP64 moments on the 6x6 Lanczos workload (8192 samples)."""
     import torch
@@ -203,9 +228,42 @@ def leg_lanczos(steps=2):
     sp = torch.from_numpy(random_sz0_spins_fast(w.N, S, 3003)).cuda()
     res = {}
     ms = timed(lambda: res.update(m.lanczos_moments(sp, exact=False, want_e1e2=False)[0]), steps, 1)
+    # exact factor count: one-hop n_c(s) plus two-hop sum_{b1} n_c(s^{b1}), times G K M
+    bonds = square_bonds(w.L)
+    spins = sp.cpu().numpy()
+    hops = 0
+    for s0 in range(0, S, 512):
+        x = spins[s0:s0 + 512].astype(np.int16)
+        anti = x[:, bonds[:, 0]] != x[:, bonds[:, 1]]
+        hops += int(anti.sum())
+        for b, (i, j) in enumerate(bonds):
+            rows = np.nonzero(anti[:, b])[0]
+            if rows.size:
+                y = x[rows].copy()
+                y[:, [i, j]] = -y[:, [i, j]]
+                hops += int((y[:, bonds[:, 0]] != y[:, bonds[:, 1]]).sum())
+    factors = float(hops) * w.G * w.n_rbm * w.n_hidden
+    flops = 13.0 * factors
     return {"workload": w.name, "S": S, "ms": ms,
             "configs_per_s": S / (ms / 1e3), "h1_per_site": res["h1"] / w.N,
-            "e_p1_per_site": res["e_p1"] / w.N}
+            "e_p1_per_site": res["e_p1"] / w.N, "factors": factors,
+            "roofline": {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12, "peak": 157.3,
+                         "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / 1e12 / 157.3,
+                         "flops_per_factor": 13}}
+
+
+def leg_logpsi(m, sp, S, w, steps=3):
+    """nqs_logpsi alone (theta GEMM + log 2cosh + LSE): 4N useful MFMA flops per
+    complex theta; the log 2cosh epilogue runs on the VALU beside it."""
+    import torch
+    out = torch.empty(S, dtype=torch.complex128, device="cuda")
+    ms = timed(lambda: out.copy_(m.logpsi(sp)), steps, 1)
+    flops = 4.0 * w.N * S * w.G * w.n_rbm * w.n_hidden
+    peak = {"fp64": 78.6, "fp32": 157.3, "bf16x2": 2500.0}[w.precision]
+    return {"S": S, "ms": ms, "configs_sym_images_per_s": S * w.n_rbm * w.G / (ms / 1e3),
+            "roofline": {"bound": "mfma", "achieved": flops / (ms / 1e3) / 1e12, "peak": peak,
+                         "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / 1e12 / peak,
+                         "flops": flops}}
 
 
 def leg_grad(m, sp, S, G, K, steps=3):
@@ -233,16 +291,30 @@ def leg_grad(m, sp, S, G, K, steps=3):
                          "flops": flops, "hbm_GBps_O_write": o_bytes / (ms / 1e3) / 1e9}}
 
 
-def leg_precision(name, steps=2):
-    """split-BF16 vs FP32 theta on the same spins, both against the oracle."""
+PRECISION_LEG_SEED = 4004
+
+
+def precision_leg_refs(name):
+    """(name, params, spins) of the two configurations whose oracle values the
+    precision leg states its errors against (computed in the CPU-baseline leg)."""
+    from workloads import WORKLOADS, draw_params, random_sz0_spins_fast
+    w = WORKLOADS[name]
+    S = w.n_chains * w.n_per_chain
+    return (name, draw_params(w), random_sz0_spins_fast(w.N, S, PRECISION_LEG_SEED)[:2])
+
+
+def leg_precision(name, refs=None, steps=2):
+    """split-BF16 vs FP32 theta on the same spins (the workload's sample count),
+    each with its errors against the oracle on two of them when the CPU-baseline
+    leg computed those (refs = (log psi, E_loc))."""
     import dataclasses
     import torch
     from paper_2206_14307_amd import NQS
     from workloads import WORKLOADS, draw_params, random_sz0_spins_fast
     out = {}
     base = WORKLOADS[name]
-    S = 4096
-    spins = random_sz0_spins_fast(base.N, S, 4004)
+    S = base.n_chains * base.n_per_chain
+    spins = random_sz0_spins_fast(base.N, S, PRECISION_LEG_SEED)
     sp = torch.from_numpy(spins).cuda()
     for prec in ("fp32", "bf16x2"):
         w = dataclasses.replace(base, precision=prec)
@@ -252,7 +324,8 @@ def leg_precision(name, steps=2):
         holder = {}
         ms = timed(lambda: holder.update(r=m.eloc(sp)), steps, 1)
         lp, el = holder["r"]
-        err = errors_vs_oracle(name, p, spins, lp.cpu().numpy(), el.cpu().numpy(), n=2)
+        err = (errors_of(lp[:2].cpu().numpy(), el[:2].cpu().numpy(), *refs) if refs is not None
+               else {"checked": 0})
         out[prec] = {"ms": ms, "configs_sym_images_per_s": S * w.n_rbm * w.G / (ms / 1e3), **err}
     out["workload"] = name
     out["S"] = S
@@ -323,7 +396,6 @@ def main():
         sys.exit(2)
 
     import torch
-    import oracle
     from paper_2206_14307_amd import NQS
     from workloads import WORKLOADS, draw_params, random_sz0_spins_fast
 
@@ -334,9 +406,12 @@ def main():
     # the CPU baseline runs first, in worker processes forked before any GPU use
     # (on uniformly random Sz = 0 configurations: at these near-uniform amplitudes
     # they follow the distribution the sampler produces)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, params, spins_np)
-    if cpu:
+    cpu, refs = None, None
+    if not args.no_cpu_baseline:
+        extra = () if args.no_legs else (precision_leg_refs("8x8_k4_m256"),)
+        cpu, refs = cpu_baseline(args.workload, params, spins_np, extra=extra)
         log(f"cpu baseline done: {cpu['value']:.3g} {cpu['unit']} on {cpu['cores']} cores")
+    spins_random = spins_np
     m = NQS.from_workload(w)
     m.set_params(torch.from_numpy(params.reshape(-1)))
     # the benchmark's configurations come from the sampler: n_chains x n_per_chain
@@ -382,8 +457,7 @@ def main():
     kern = {k: m.profile_read(k, reset=True) for k in ("theta", "lse", "eloc_bonds", "eloc_finish")}
     m.profile(False)
 
-    om = oracle.Model.from_workload(w)
-    nc = n_antiparallel(spins_np, om.lat.bonds).astype(np.int64)
+    nc = n_antiparallel(spins_np, square_bonds(w.L)).astype(np.int64)
     factors_per_step = int(nc.sum()) * w.G * w.n_rbm * w.n_hidden
     ms_bonds, n_bonds = kern["eloc_bonds"]
     launches_per_step = n_bonds / args.steps
@@ -404,8 +478,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    errs = errors_vs_oracle(args.workload, params, spins_np, lp.cpu().numpy(), el.cpu().numpy())
-    log(f"errors vs oracle: {errs}")
+    errs = None
+    if refs is not None:
+        # the oracle's values come from the CPU-baseline leg: evaluate the same
+        # configurations on the GPU path and compare
+        chk = torch.from_numpy(spins_random[refs["idx"]]).cuda()
+        glp, gel = m.eloc(chk)
+        errs = errors_of(glp.cpu().numpy(), gel.cpu().numpy(), refs["logpsi"], refs["eloc"])
+        errs["configurations"] = "the CPU-baseline sample (uniform Sz = 0)"
+        log(f"errors vs oracle: {errs}")
     result = {
         "metric": "configs*sym-images/s for logpsi+E_loc, 1 GPU, at stated energy error",
         "value": S * w.n_rbm * w.G / (ms_step / 1e3),
@@ -424,9 +505,12 @@ def main():
     if not args.no_legs:
         legs["grad"] = leg_grad(m, sp, S, w.G, w.n_rbm)
         log(f"grad leg: {legs['grad']['ms']:.2f} ms")
+        legs["logpsi"] = leg_logpsi(m, sp, S, w)
+        log(f"logpsi leg: {legs['logpsi']['ms']:.2f} ms")
         legs["lanczos_two_hop"] = leg_lanczos()
         log(f"lanczos leg: {legs['lanczos_two_hop']['ms']:.2f} ms")
-        legs["bf16x2_vs_fp32_8x8"] = leg_precision("8x8_k4_m256")
+        legs["bf16x2_vs_fp32_8x8"] = leg_precision(
+            "8x8_k4_m256", None if refs is None or not refs["extra"] else refs["extra"][0])
         log("precision leg done")
         legs["sr_10x10"] = leg_sr()
         log(f"sr leg: {legs['sr_10x10']['ms_sr']:.1f} ms")
