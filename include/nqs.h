@@ -186,6 +186,14 @@ nqs_status nqs_sample(nqs_ctx* ctx, int64_t n_chains, int64_t n_per_chain, int32
                       float* acc_rate_out, int32_t* n_skip_out, void* ws, size_t ws_bytes,
                       hipStream_t stream);
 
+/* Arithmetic form of the exchange factors (Sec. 3.2 Eq. (10), Sec. 3.3).
+ * direct_only = 0 (default): where their range checks pass, the kernels take
+ * the one-hop factors s + t T as T (t + s / T) (checked per parameter set)
+ * and the two-hop factors s2 A + T2 B as A (s2 + T2 B / A) (checked per
+ * first hop and image); direct_only = 1: always the direct products.  Both
+ * give the same results within rounding. */
+nqs_status nqs_set_factor_form(nqs_ctx* ctx, int direct_only);
+
 /* Per-kernel timing for benchmarks.  While enabled, every kernel launch of
  * this context is bracketed by HIP events on the call's stream.
  * nqs_profile_read synchronises those events and returns, for kernel id

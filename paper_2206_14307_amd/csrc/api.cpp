@@ -486,6 +486,14 @@ nqs_status nqs_enumerate_sz0(nqs_ctx* c, int8_t* spins_out, int64_t cap, int64_t
   return e == hipSuccess ? NQS_OK : hip_fail(c, e, "enumerate_sz0 launch");
 }
 
+nqs_status nqs_set_factor_form(nqs_ctx* c, int direct_only) {
+  if (!c) return NQS_ERR_ARG;
+  if (direct_only != 0 && direct_only != 1)
+    return fail(c, NQS_ERR_ARG, "set_factor_form: direct_only must be 0 or 1");
+  c->direct_only = direct_only == 1;
+  return NQS_OK;
+}
+
 nqs_status nqs_profile_enable(nqs_ctx* c, int on) {
   if (!c) return NQS_ERR_ARG;
   c->prof.on = on != 0;

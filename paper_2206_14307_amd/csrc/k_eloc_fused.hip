@@ -387,7 +387,8 @@ hipError_t run_if_fits(const nqs_ctx* c, const int8_t* spins, int64_t S, double*
     return hipErrorNotSupported;
   } else {
     if constexpr (FusedCfg<N, PREC, K, M, true>::LDS <= kLdsLimit)
-      if (c->par.recip_ok) return run<N, PREC, K, M, true>(c, spins, S, part, logpsi, eloc, es, st);
+      if (c->par.recip_ok && !c->direct_only)
+        return run<N, PREC, K, M, true>(c, spins, S, part, logpsi, eloc, es, st);
     return run<N, PREC, K, M, false>(c, spins, S, part, logpsi, eloc, es, st);
   }
 }

@@ -187,29 +187,76 @@ hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t, 
 
 
 // Two-hop H^2 terms (Sec. 3.3) for single-RBM models with register-resident
-// tanh(theta) rows.  For exchanges b1 then b2 with signs s1, s2 (orientation
+// tanh(theta).  For exchanges b1 then b2 with signs s1, s2 (orientation
 // folded) and unsigned T1 = tanh D1, T2 = tanh D2:
 //   s1 s2 cosh(theta + s1 D1 + s2 D2)/(cosh theta cosh D1 cosh D2) = s2 A + T2 B,
 //   A = s1 + t T1,  B = s1 t + T1,
 // and (s1 s2)^M = 1, so the second-hop product is prod_h (s2 A_h + T2_h B_h)
-// and the first-hop product prod_h A_h.  One wavefront per (sample, first-hop
-// slot, 32-image tile); the +T table stays in LDS for the launch.
+// and the first-hop product prod_h A_h.
+//
+// One wavefront per (sample, first-hop slot, 32-image tile).  The two lanes
+// of an image split the hidden units by parity (lane half = lane / 32 takes
+// h = 2j + half), both walk every second-hop bond, and the two partial
+// products are joined with v_permlane32_swap, which serves the two bonds of a
+// pass at once (bond 0 complete in lanes 0..31, bond 1 in lanes 32..63).  The
+// +T table stays in LDS for the launch, each row ordered [even h | odd h].
+//
+// Ratio form: f = s2 A + T2 B = A (s2 + T2 Q) with Q = B / A.  Once per
+// (first hop, image) Q replaces t in registers and every second-hop product
+// starts from prod A over the lane's units: 8 VALU operations per factor
+// instead of about 11.  Used when every suffix product of |A|^2 along the
+// lane's units lies in 2^[-120, 120] (binary exponents summed exactly) on all
+// lanes of the wave; otherwise t is reloaded and the direct form runs.
+__device__ __forceinline__ int ilogb_bits(float v) { return ((__float_as_int(v) >> 23) & 0xff) - 127; }
+__device__ __forceinline__ int ilogb_bits(double v) {
+  return (int)((__double_as_longlong(v) >> 52) & 0x7ff) - 1023;
+}
+__device__ __forceinline__ float rcp_fast(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double rcp_fast(double v) { return 1.0 / v; }
+
+__device__ __forceinline__ void swap32(float& x, float& y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap32(double& x, double& y) {
+  const unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32),
+                                                   false, false);
+  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+// (x of lanes 0..31) * (x of lanes 32..63), in every lane
+template <typename R>
+__device__ __forceinline__ void join_halves(R& xr, R& xi) {
+  R yr = xr, yi = xi;
+  swap32(xr, yr);
+  swap32(xi, yi);
+  const R nr = xr * yr - xi * yi;
+  xi = xr * yi + xi * yr;
+  xr = nr;
+}
+
 template <typename R, int N, int M>
 __global__ __launch_bounds__(64 * kRegWaves) void twohop_reg_kernel(
     const int8_t* __restrict__ spins, int64_t S, int G, int n_htiles,
     const int32_t* __restrict__ bonds, const double* __restrict__ bond_J,
     const int32_t* __restrict__ bmap, const R* __restrict__ t, const R* __restrict__ w,
-    const R* __restrict__ Tpm, const R* __restrict__ F, double* __restrict__ partial2) {
+    const R* __restrict__ Tpm, const R* __restrict__ F, double* __restrict__ partial2,
+    int allow_ratio) {
   using Cfg = RegCfg<R, N, 1, M>;
-  constexpr int NB = Cfg::NB, ST = Cfg::STRIDE;
+  constexpr int NB = Cfg::NB, ST = Cfg::STRIDE, MH = M / 2;
   __shared__ __align__(16) R Tl[NB * ST];
   __shared__ int16_t lists[kRegWaves][2][NB];
   __shared__ int8_t rows[kRegWaves][N];
   for (int idx = threadIdx.x; idx < NB * M; idx += blockDim.x) {
     const int beta = idx / M, h = idx % M;
     const R* src = Tpm + ((size_t)beta * 2 * M + h) * 2;
-    Tl[beta * ST + 2 * h] = src[0];
-    Tl[beta * ST + 2 * h + 1] = src[1];
+    const int pos = (h & 1) * MH + (h >> 1);             // [even h | odd h]
+    Tl[beta * ST + 2 * pos] = src[0];
+    Tl[beta * ST + 2 * pos + 1] = src[1];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -241,49 +288,101 @@ __global__ __launch_bounds__(64 * kRegWaves) void twohop_reg_kernel(
       diag2 += 0.25 * bond_J[b] * (double)(row2[bonds[2 * b]] * row2[bonds[2 * b + 1]]);
     diag2 = wave_sum(diag2);
 
-    const int g = tile * 32 + (lane & 31);
-    const int half = lane >> 5;
-    R tr[M], ti[M];
+    // lane-derived values are recomputed per item rather than hoisted out of
+    // the item loop and kept live (or spilled) across it
+    int lane_i = lane;
+    asm volatile("" : "+v"(lane_i));
+    const int half = lane_i >> 5;
+    const int g = tile * 32 + (lane_i & 31);
+    // this lane's units h = 2j + half: tanh(theta) from the [S][M/8][G][8] layout
+    R tr[MH], ti[MH];
+    auto load_t = [&](int gg) {
 #pragma unroll
-    for (int ht = 0; ht < M / 8; ++ht) {
-      const R* tp = t + (((size_t)s * n_htiles + ht) * G + g) * 16;
+      for (int ht = 0; ht < M / 8; ++ht) {
+        const R* tp = t + (((size_t)s * n_htiles + ht) * G + gg) * 16;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        tr[8 * ht + e] = tp[2 * e];
-        ti[8 * ht + e] = tp[2 * e + 1];
+        for (int e = 0; e < 4; ++e) {
+          tr[4 * ht + e] = tp[2 * (2 * e + half)];
+          ti[4 * ht + e] = tp[2 * (2 * e + half) + 1];
+        }
       }
-    }
+    };
+    load_t(g);
     const R wr = w[((size_t)s * G + g) * 2], wi = w[((size_t)s * G + g) * 2 + 1];
     const int v1 = bmap[(size_t)g * NB + b1];
     const int beta1 = v1 >> 1;
     const int s1b = -(int)srow[i1];
     const int s1i = (v1 & 1) ? -s1b : s1b;
     const R s1 = (R)s1i;
-    const R* T1 = Tl + beta1 * ST;
+    const R* T1 = Tl + beta1 * ST + half * M;           // this lane's half of the row
     const R* f1 = F + ((size_t)beta1 * 2 + (s1i > 0 ? 0 : 1)) * 2;
     const R g1r = f1[0] * wr - f1[1] * wi, g1i = f1[0] * wi + f1[1] * wr;   // w F1
     double accr = 0.0, acci = 0.0;
-    if (half == 0) {
-      R pr = 1, pi = 0;
+
+    // ratio form: Q, prod A over the lane's units and the exponent check in one pass
+    R par = 1, pai = 0;
+    bool ok = allow_ratio != 0;
+    {
+      int esum = 0, pmax = 0, pmin = 0;              // suffix sums = total - prefix sums
 #pragma unroll
-      for (int h = 0; h < M; ++h) {
-        const R Tr = T1[2 * h], Ti = T1[2 * h + 1];
-        const R a = fmaf_t(tr[h], Tr, fmaf_t(-ti[h], Ti, s1));
-        const R b = fmaf_t(tr[h], Ti, ti[h] * Tr);
-        const R nr = fmaf_t(pr, a, -(pi * b));
-        pi = fmaf_t(pr, b, pi * a);
-        pr = nr;
+      for (int j = 0; j < MH; ++j) {
+        if ((j & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+        const R Tr = T1[2 * j], Ti = T1[2 * j + 1];
+        const R ar = fmaf_t(tr[j], Tr, fmaf_t(-ti[j], Ti, s1));
+        const R ai = fmaf_t(tr[j], Ti, ti[j] * Tr);
+        const R br = fmaf_t(s1, tr[j], Tr), bi = fmaf_t(s1, ti[j], Ti);
+        const R a2 = ar * ar + ai * ai;
+        ok &= (a2 > R(0)) & (a2 < R(INFINITY));       // no short-circuit branches
+        pmax = max(pmax, esum);
+        pmin = min(pmin, esum);
+        esum += ilogb_bits(a2);
+        const R inv = rcp_fast(a2);
+        tr[j] = (br * ar + bi * ai) * inv;           // Q = B conj(A) / |A|^2
+        ti[j] = (bi * ar - br * ai) * inv;
+        const R nr = fmaf_t(par, ar, -(pai * ai));
+        pai = fmaf_t(par, ai, pai * ar);
+        par = nr;
       }
-      accr += diag2 * (double)(g1r * pr - g1i * pi);
-      acci += diag2 * (double)(g1r * pi + g1i * pr);
+      ok &= (esum - pmin <= 120) & (esum - pmax >= -120);
     }
-    for (int i0 = half; i0 < nc2; i0 += 4) {
+    // Q is used only on the ratio branch: pin it here so that the compiler
+    // does not sink its computation into the branch and keep A, B live
+#pragma unroll
+    for (int j = 0; j < MH; ++j) asm volatile("" : "+v"(tr[j]), "+v"(ti[j]));
+    const bool ratio = __all(ok);
+    if (!ratio) {
+      int g2 = g;                                // fresh addresses for the reload
+      asm volatile("" : "+v"(g2));
+      load_t(g2);
+    }
+    {
+      // first-hop product over all units (both halves)
+      R pr = par, pi = pai;
+      if (!ratio) {
+        pr = 1;
+        pi = 0;
+#pragma unroll
+        for (int j = 0; j < MH; ++j) {
+          const R Tr = T1[2 * j], Ti = T1[2 * j + 1];
+          const R a = fmaf_t(tr[j], Tr, fmaf_t(-ti[j], Ti, s1));
+          const R b = fmaf_t(tr[j], Ti, ti[j] * Tr);
+          const R nr = fmaf_t(pr, a, -(pi * b));
+          pi = fmaf_t(pr, b, pi * a);
+          pr = nr;
+        }
+      }
+      join_halves(pr, pi);
+      if (half == 0) {
+        accr += diag2 * (double)(g1r * pr - g1i * pi);
+        acci += diag2 * (double)(g1r * pi + g1i * pr);
+      }
+    }
+    for (int i0 = 0; i0 < nc2; i0 += 2) {
       int beta[2], sidx[2];
-      R sgn[2], valid[2];
+      R sgn[2];
 #pragma unroll
       for (int n = 0; n < 2; ++n) {
-        const int ii = i0 + 2 * n;
-        valid[n] = ii < nc2 ? R(1) : R(0);
+        const int ii = i0 + n;
         const int b = l2[ii < nc2 ? ii : i0];
         const int v = bmap[(size_t)g * NB + b];
         beta[n] = v >> 1;
@@ -292,42 +391,70 @@ __global__ __launch_bounds__(64 * kRegWaves) void twohop_reg_kernel(
         sgn[n] = (R)sp;
         sidx[n] = sp > 0 ? 0 : 1;
       }
-      const R* U0 = Tl + beta[0] * ST;
-      const R* U1 = Tl + beta[1] * ST;
-      R p0r = 1, p0i = 0, p1r = 1, p1i = 0;
+      const R* U0 = Tl + beta[0] * ST + half * M;
+      const R* U1 = Tl + beta[1] * ST + half * M;
+      R p0r, p0i, p1r, p1i;
+      if (ratio) {
+        p0r = p1r = par;
+        p0i = p1i = pai;
 #pragma unroll
-      for (int h = 0; h < M; ++h) {
-        // keep the scheduler from hoisting every LDS load of the unrolled loop
-        if ((h & 3) == 0) __builtin_amdgcn_sched_barrier(0);
-        const R Tr = T1[2 * h], Ti = T1[2 * h + 1];
-        const R Ar = fmaf_t(tr[h], Tr, fmaf_t(-ti[h], Ti, s1));
-        const R Ai = fmaf_t(tr[h], Ti, ti[h] * Tr);
-        const R Br = fmaf_t(s1, tr[h], Tr), Bi = fmaf_t(s1, ti[h], Ti);
-        {
-          const R Vr = U0[2 * h], Vi = U0[2 * h + 1];
-          const R fr = fmaf_t(Vr, Br, fmaf_t(-Vi, Bi, sgn[0] * Ar));
-          const R fi = fmaf_t(Vr, Bi, fmaf_t(Vi, Br, sgn[0] * Ai));
-          const R nr = fmaf_t(p0r, fr, -(p0i * fi));
-          p0i = fmaf_t(p0r, fi, p0i * fr);
-          p0r = nr;
+        for (int j = 0; j < MH; ++j) {
+          if ((j & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+          const R Qr = tr[j], Qi = ti[j];
+          {
+            const R Vr = U0[2 * j], Vi = U0[2 * j + 1];
+            const R fr = fmaf_t(Vr, Qr, fmaf_t(-Vi, Qi, sgn[0]));
+            const R fi = fmaf_t(Vr, Qi, Vi * Qr);
+            const R nr = fmaf_t(p0r, fr, -(p0i * fi));
+            p0i = fmaf_t(p0r, fi, p0i * fr);
+            p0r = nr;
+          }
+          {
+            const R Vr = U1[2 * j], Vi = U1[2 * j + 1];
+            const R fr = fmaf_t(Vr, Qr, fmaf_t(-Vi, Qi, sgn[1]));
+            const R fi = fmaf_t(Vr, Qi, Vi * Qr);
+            const R nr = fmaf_t(p1r, fr, -(p1i * fi));
+            p1i = fmaf_t(p1r, fi, p1i * fr);
+            p1r = nr;
+          }
         }
-        {
-          const R Vr = U1[2 * h], Vi = U1[2 * h + 1];
-          const R fr = fmaf_t(Vr, Br, fmaf_t(-Vi, Bi, sgn[1] * Ar));
-          const R fi = fmaf_t(Vr, Bi, fmaf_t(Vi, Br, sgn[1] * Ai));
-          const R nr = fmaf_t(p1r, fr, -(p1i * fi));
-          p1i = fmaf_t(p1r, fi, p1i * fr);
-          p1r = nr;
+      } else {
+        p0r = p1r = 1;
+        p0i = p1i = 0;
+#pragma unroll
+        for (int j = 0; j < MH; ++j) {
+          if ((j & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+          const R Tr = T1[2 * j], Ti = T1[2 * j + 1];
+          const R Ar = fmaf_t(tr[j], Tr, fmaf_t(-ti[j], Ti, s1));
+          const R Ai = fmaf_t(tr[j], Ti, ti[j] * Tr);
+          const R Br = fmaf_t(s1, tr[j], Tr), Bi = fmaf_t(s1, ti[j], Ti);
+          {
+            const R Vr = U0[2 * j], Vi = U0[2 * j + 1];
+            const R fr = fmaf_t(Vr, Br, fmaf_t(-Vi, Bi, sgn[0] * Ar));
+            const R fi = fmaf_t(Vr, Bi, fmaf_t(Vi, Br, sgn[0] * Ai));
+            const R nr = fmaf_t(p0r, fr, -(p0i * fi));
+            p0i = fmaf_t(p0r, fi, p0i * fr);
+            p0r = nr;
+          }
+          {
+            const R Vr = U1[2 * j], Vi = U1[2 * j + 1];
+            const R fr = fmaf_t(Vr, Br, fmaf_t(-Vi, Bi, sgn[1] * Ar));
+            const R fi = fmaf_t(Vr, Bi, fmaf_t(Vi, Br, sgn[1] * Ai));
+            const R nr = fmaf_t(p1r, fr, -(p1i * fi));
+            p1i = fmaf_t(p1r, fi, p1i * fr);
+            p1r = nr;
+          }
         }
       }
-#pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        const R pr = n ? p1r : p0r, pi = n ? p1i : p0i;
-        const R* f2 = F + ((size_t)beta[n] * 2 + sidx[n]) * 2;
-        const R hr = f2[0] * g1r - f2[1] * g1i, hi = f2[0] * g1i + f2[1] * g1r;
-        accr += (double)(valid[n] * (hr * pr - hi * pi));
-        acci += (double)(valid[n] * (hr * pi + hi * pr));
-      }
+      // join the halves: lanes 0..31 get bond 0's product, lanes 32..63 bond 1's
+      swap32(p0r, p1r);
+      swap32(p0i, p1i);
+      const R pr = p0r * p1r - p0i * p1i, pi = p0r * p1i + p0i * p1r;
+      const bool valid = i0 + half < nc2;
+      const R* f2 = F + ((size_t)beta[half] * 2 + sidx[half]) * 2;
+      const R hr = f2[0] * g1r - f2[1] * g1i, hi = f2[0] * g1i + f2[1] * g1r;
+      accr += valid ? (double)(hr * pr - hi * pi) : 0.0;
+      acci += valid ? (double)(hr * pi + hi * pr) : 0.0;
     }
     accr = wave_sum(accr);
     acci = wave_sum(acci);
@@ -348,7 +475,7 @@ hipError_t run_twohop(const nqs_ctx* c, const int8_t* spins, int64_t S, const vo
   blocks = std::min<int64_t>(blocks, c->n_cu > 0 ? c->n_cu : 256);
   twohop_reg_kernel<R, N, M><<<(unsigned)blocks, 64 * kRegWaves, 0, st>>>(
       spins, S, c->G, c->n_htiles, c->dev.bonds, c->dev.bond_J, c->dev.bmap, (const R*)t,
-      (const R*)w, (const R*)c->par.Tpm, (const R*)c->par.F, partial2);
+      (const R*)w, (const R*)c->par.Tpm, (const R*)c->par.F, partial2, c->direct_only ? 0 : 1);
   return hipGetLastError();
 }
 

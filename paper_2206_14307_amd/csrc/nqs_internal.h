@@ -92,6 +92,7 @@ struct nqs_ctx {
   int64_t P = 0;
   int prec = 1;
   int64_t sector_count = -1;      // C(N, N/2), -1 if it overflows int64
+  bool direct_only = false;       // nqs_set_factor_form: direct exchange-factor forms only
   int n_htiles = 0;               // K*M/8 hidden tiles of 8 units (16 interleaved rows)
   int nk = 0;                     // MFMA K-steps over the site axis
   nqs::Geometry geo;

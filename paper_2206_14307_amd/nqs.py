@@ -23,8 +23,8 @@ OP = {"logpsi": 0, "eloc": 1, "moments": 2, "grad": 3, "sr": 4, "sample": 5}
 
 EXPORTS = ["nqs_create", "nqs_destroy", "nqs_num_params", "nqs_workspace_bytes", "nqs_set_params",
            "nqs_logpsi", "nqs_eloc", "nqs_lanczos_moments", "nqs_grad", "nqs_sr_solve",
-           "nqs_chain_init", "nqs_sample", "nqs_enumerate_sz0", "nqs_profile_enable",
-           "nqs_profile_read", "nqs_status_str", "nqs_last_error"]
+           "nqs_chain_init", "nqs_sample", "nqs_enumerate_sz0", "nqs_set_factor_form",
+           "nqs_profile_enable", "nqs_profile_read", "nqs_status_str", "nqs_last_error"]
 KERNELS = {"theta": 0, "lse": 1, "eloc_bonds": 2, "eloc_finish": 3, "twohop": 4,
            "twohop_finish": 5, "moments": 6, "grad": 7, "sample": 8, "sr": 9, "gram": 10,
            "cholesky": 11}
@@ -75,6 +75,7 @@ def load_library(path: str = LIB_PATH):
         "nqs_chain_init": ([vp, vp, i64, u64, vp, vp], C.c_int),
         "nqs_sample": ([vp, i64, i64, i32, i32, u64, vp, vp, vp, vp, vp, C.c_size_t, vp], C.c_int),
         "nqs_enumerate_sz0": ([vp, vp, i64, C.POINTER(i64), vp], C.c_int),
+        "nqs_set_factor_form": ([vp, C.c_int], C.c_int),
         "nqs_profile_enable": ([vp, C.c_int], C.c_int),
         "nqs_profile_read": ([vp, C.c_int, C.POINTER(dbl), C.POINTER(i64), C.c_int], C.c_int),
         "nqs_status_str": ([C.c_int], C.c_char_p),
@@ -168,6 +169,10 @@ class NQS:
         self._check(self.lib.nqs_set_params(self._ctx, _ptr(torch.view_as_real(p)), _stream()),
                     "nqs_set_params")
         self.params = p
+
+    def set_factor_form(self, direct_only):
+        self._check(self.lib.nqs_set_factor_form(self._ctx, int(bool(direct_only))),
+                    "nqs_set_factor_form")
 
     def sector_size(self):
         n = C.c_int64(0)

@@ -19,10 +19,11 @@ from workloads import WORKLOADS, draw_params, random_sz0_spins
 pytestmark = pytest.mark.gpu
 
 
-def make(w, params):
+def make(w, params, direct=False):
     from paper_2206_14307_amd import NQS
     m = NQS.from_workload(w)
     m.set_params(torch.from_numpy(params.reshape(-1)))
+    m.set_factor_form(direct)          # direct: the plain product forms of the factors
     return m
 
 
@@ -66,9 +67,10 @@ def test_eloc_full_sector_fp64(c1_case):
     assert max_rel_err(gel.cpu().numpy(), e1) < TOL["fp64"]
 
 
-def test_exact_moments_fp64(c1_case):
+@pytest.mark.parametrize("direct", [False, True])
+def test_exact_moments_fp64(c1_case, direct):
     w, p, om, spins, lp, e1, e2 = c1_case
-    m = make(w, p)
+    m = make(w, p, direct)
     res, e12 = m.lanczos_moments(cuda(spins), exact=True)
     e12 = e12.cpu().numpy()
     assert max_rel_err(e12[:, 0], e1) < TOL["fp64"]
@@ -120,9 +122,10 @@ def c2_case():
     return w, p, om, spins
 
 
-def test_logpsi_eloc_fp32(c2_case):
+@pytest.mark.parametrize("direct", [False, True])
+def test_logpsi_eloc_fp32(c2_case, direct):
     w, p, om, spins = c2_case
-    m = make(w, p)
+    m = make(w, p, direct)
     glp, gel = m.eloc(cuda(spins))
     assert max_logpsi_err(glp.cpu().numpy(), oracle.logpsi(om, p, spins)) < TOL["fp32"]
     assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, spins)) < TOL["fp32"]
@@ -150,12 +153,13 @@ def test_stress_fp32_b1_pi():
     assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp)) < 1e-4
 
 
-def test_twohop_fp32():
+@pytest.mark.parametrize("direct", [False, True])
+def test_twohop_fp32(direct):
     w = WORKLOADS["6x6_fp32_lanczos"]
     p = stress_params(w, 0.05, 4)
     om = oracle.Model.from_workload(w)
     sp = random_sz0_spins(w.N, 2, 11)
-    m = make(w, p)
+    m = make(w, p, direct)
     res, e12 = m.lanczos_moments(cuda(sp), exact=False)
     e12 = e12.cpu().numpy()
     e1 = oracle.eloc_direct(om, p, sp)
@@ -167,7 +171,8 @@ def test_twohop_fp32():
     assert abs(res["e_p1"] - ref["e_p1"]) < TOL["fp32"] * abs(ref["h1"])
 
 
-def test_twohop_fp32_4x4_exact_mode(sector16):
+@pytest.mark.parametrize("direct", [False, True])
+def test_twohop_fp32_4x4_exact_mode(sector16, direct):
     w = dataclasses.replace(WORKLOADS["4x4_fp64_exact"], precision="fp32", is_complex=True,
                             n_hidden=16)
     p = stress_params(w, 0.1, 6)
@@ -178,7 +183,7 @@ def test_twohop_fp32_4x4_exact_mode(sector16):
     H = oracle.hamiltonian_sector(om, masks)
     e1 = (H @ psi) / psi
     e2 = (H @ (H @ psi)) / psi
-    m = make(w, p)
+    m = make(w, p, direct)
     res, e12 = m.lanczos_moments(cuda(spins), exact=True)
     e12 = e12.cpu().numpy()
     assert max_rel_err(e12[:, 0], e1) < TOL["fp32"]
