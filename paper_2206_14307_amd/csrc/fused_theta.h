@@ -34,23 +34,44 @@ __device__ __forceinline__ void theta_block(
   for (int k = 0; k < K; ++k) {
     R pr = R(1), pi = R(0);
     int pe = 0;
+    uint32_t par = 0u;
     double sax = 0.0;
 #pragma unroll
     for (int tt = 0; tt < TPR; ++tt) {
       const int ht = k * TPR + tt;
-      typename T::Acc acc = typename T::Acc{0, 0, 0, 0};
+      const int h0 = 8 * ht + 2 * q;
+      typename T::Acc acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = bias[2 * h0 + v];   // start from the biases
 #pragma unroll
       for (int kk = 0; kk < NK; ++kk) acc = mfma(Wl[(ht * NK + kk) * 64 + lane], bx[kk], acc);
-      const int h0 = 8 * ht + 2 * q;
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const R x = (R)acc[2 * u] + bias[2 * (h0 + u)];
-        const R y = (R)acc[2 * u + 1] + bias[2 * (h0 + u) + 1];
-        logcosh_step<R, true>(x, y, pr, pi, sax, tr[2 * ht + u], ti[2 * ht + u]);
-      }
+      const R ax0 = logcosh_step<R, true>((R)acc[0], (R)acc[1], pr, pi, par, tr[2 * ht],
+                                          ti[2 * ht]);
+      const R ax1 = logcosh_step<R, true>((R)acc[2], (R)acc[3], pr, pi, par, tr[2 * ht + 1],
+                                          ti[2 * ht + 1]);
+      sax += (double)(ax0 + ax1);
       if ((tt & 7) == 7) renorm(pr, pi, pe);
     }
     renorm(pr, pi, pe);
+    apply_parity(pr, pi, par);
+    // a . (g sigma): FP32 / FP64 fragments hold x_j for j = q mod 4
+    R xr = R(0), xi = R(0);
+    const R* ak = avec + (size_t)k * N * 2;
+    if constexpr (PREC != NQS_BF16X2) {
+#pragma unroll
+      for (int kk = 0; kk < NK; ++kk) {
+        xr = fmaf_t(bx[kk], ak[2 * (4 * kk + q)], xr);
+        xi = fmaf_t(bx[kk], ak[2 * (4 * kk + q) + 1], xi);
+      }
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < N / 4; ++jj) {
+        const int j = 4 * jj + q;
+        const R xj = R(0.5) * (R)srow[prow[j]];
+        xr = fmaf_t(xj, ak[2 * j], xr);
+        xi = fmaf_t(xj, ak[2 * j + 1], xi);
+      }
+    }
     int E = pe;
 #pragma unroll
     for (int o = 16; o <= 32; o <<= 1) {
@@ -60,24 +81,13 @@ __device__ __forceinline__ void theta_block(
       pr = nr;
       E += __shfl_xor(E, o, 64);
       sax += __shfl_xor(sax, o, 64);
+      xr += __shfl_xor(xr, o, 64);
+      xi += __shfl_xor(xi, o, 64);
     }
-    double axr = 0.0, axi = 0.0;
-    const R* ak = avec + (size_t)k * N * 2;
-#pragma unroll
-    for (int jj = 0; jj < N / 4; ++jj) {
-      const int j = 4 * jj + q;
-      const double xj = 0.5 * (double)srow[prow[j]];
-      axr += xj * (double)ak[2 * j];
-      axi += xj * (double)ak[2 * j + 1];
-    }
-    axr += __shfl_xor(axr, 16, 64);
-    axi += __shfl_xor(axi, 16, 64);
-    axr += __shfl_xor(axr, 32, 64);
-    axi += __shfl_xor(axi, 32, 64);
-    Er[k] = axr + sax + (double)E * 0.69314718055994530942;
+    Er[k] = (double)xr + sax + (double)E * 0.69314718055994530942;
     Pr[k] = pr;
     Pi[k] = pi;
-    Ai[k] = (R)axi;
+    Ai[k] = xi;
   }
 }
 

@@ -147,6 +147,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
         float Pr[kWideBonds], Pi[kWideBonds];
         float lpr = 1.f, lpi = 0.f;
         int lpe = 0;
+        uint32_t lpar = 0u;
         double sax = 0.0;
 
         for (int ch = 0; ch < NCH; ++ch, ++gc) {
@@ -165,20 +166,22 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
 #pragma unroll
           for (int tt = 0; tt < kHC / 8; ++tt) {
             const int ht = (kHC / 8) * ch + tt;
-            typename T::Acc acc = typename T::Acc{0, 0, 0, 0};
+            const int h0 = 8 * ht + 2 * q;
+            typename T::Acc acc;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] = bias[2 * h0 + v];   // start from the biases
 #pragma unroll
             for (int kk = 0; kk < NK; ++kk) acc = mfma(wfrag[((size_t)ht * NK + kk) * 64 + lane], bx[kk], acc);
-            const int h0 = 8 * ht + 2 * q;
+            float axs = 0.f;
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-              const float x = acc[2 * u] + bias[2 * (h0 + u)];
-              const float y = acc[2 * u + 1] + bias[2 * (h0 + u) + 1];
               float tr, ti;
-              logcosh_step<float, true>(x, y, lpr, lpi, sax, tr, ti);
+              axs += logcosh_step<float, true>(acc[2 * u], acc[2 * u + 1], lpr, lpi, lpar, tr, ti);
               const int hl = 8 * tt + 2 * q + u;
               tx[wv][c * kXS + 2 * hl] = tr;
               tx[wv][c * kXS + 2 * hl + 1] = ti;
             }
+            sax += (double)axs;
           }
           renorm(lpr, lpi, lpe);
           wave_sync_lds();
@@ -219,6 +222,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
             Pr[jb] = ar; Pi[jb] = ai; Pr[jb + 1] = br; Pi[jb + 1] = bi;
           }
           if (ch % CPR == CPR - 1) {           // RBM k complete: weight and sum
+            apply_parity(lpr, lpi, lpar);
             int E = lpe;
             float pr = lpr, pi = lpi;
             double sx = sax;
@@ -265,7 +269,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
               denr += (double)ur;
               deni += (double)ui;
             }
-            lpr = 1.f; lpi = 0.f; lpe = 0; sax = 0.0;
+            lpr = 1.f; lpi = 0.f; lpe = 0; lpar = 0u; sax = 0.0;
           }
           NQS_STAGE_STORE(gc & 1 ? 0 : 1)
           __syncthreads();

@@ -10,19 +10,27 @@
 // Re/Im theta of hidden units 8 ht + 2q, 8 ht + 2q + 1 for image c, so the
 // epilogue is lane-local.
 //
-// Epilogue: with x = Re theta, y = Im theta, e = exp(-2|x|),
-//   2 cosh(theta) = exp(|x|) * c,  c = (1+e) cos y + i sgn(x) (1-e) sin y,
-//   tanh(theta)   = (sgn(x)(1-e^2) + i 4 e sin y cos y) / |c|^2,
-// so sum_h log 2cosh(theta_h) = sum_h |x_h| + log prod_h c_h, with the product
-// kept as (mantissa, binary exponent) -- one log/atan2 per (RBM, image)
-// instead of one per hidden unit.  sum |x| is accumulated in FP64.
+// Epilogue (theta_common.h): with x = Re theta, y = Im theta = k pi + r,
+// e = exp(-2|x|),
+//   2 cosh(theta) = exp(|x|) (-1)^k c,  c = (1+e) cos r + i sgn(x) (1-e) sin r,
+//   tanh(theta)   = (sgn(x)(1-e^2) + i 4 e sin r cos r) / |c|^2,
+// so sum_h log 2cosh(theta_h) = sum_h |x_h| + log((-1)^{sum k} prod_h c_h), with
+// the product kept as (mantissa, binary exponent) -- one log/atan2 per (RBM,
+// image) instead of one per hidden unit.  The accumulators start from the
+// biases; sum |x| is added in FP64 once per tile (two units per lane).
+//
+// After the last tile of an RBM the four lane groups q (different hidden
+// units of one image) are joined with shuffles; a.(g sigma) comes from the B
+// fragments already in registers (FP32 / FP64: lane q holds x_j for
+// j = q mod 4).  Lane group q then finishes column block q mod CB, so each
+// lane evaluates one log and one atan2.
 #include "theta_common.h"
 
 namespace nqs {
 
 namespace {
 
-template <int N, int PREC, int CB>
+template <int N, int PREC, int CB, bool WANT_T>
 __global__ __launch_bounds__(256) void theta_kernel(
     const int8_t* __restrict__ spins, int64_t S, const uint8_t* __restrict__ perm, int G,
     const typename ThetaTraits<PREC>::AFrag* __restrict__ wfrag,
@@ -57,19 +65,25 @@ __global__ __launch_bounds__(256) void theta_kernel(
   for (int k = 0; k < K; ++k) {
     R pr[CB], pi[CB];
     int pe[CB];
+    uint32_t par[CB];
     double sax[CB];
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
       pr[b] = R(1);
       pi[b] = R(0);
       pe[b] = 0;
+      par[b] = 0u;
       sax[b] = 0.0;
     }
     for (int tt = 0; tt < tiles_per_rbm; ++tt) {
       const int ht = k * tiles_per_rbm + tt;
+      const int h0 = 8 * ht + 2 * q;
+      typename T::Acc b0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b0[v] = bias[2 * h0 + v];
       typename T::Acc acc[CB];
 #pragma unroll
-      for (int b = 0; b < CB; ++b) acc[b] = typename T::Acc{0, 0, 0, 0};
+      for (int b = 0; b < CB; ++b) acc[b] = b0;
       const typename T::AFrag* ap = wfrag + (size_t)ht * NK * 64 + lane;
 #pragma unroll
       for (int kk = 0; kk < NK; ++kk) {
@@ -77,25 +91,20 @@ __global__ __launch_bounds__(256) void theta_kernel(
 #pragma unroll
         for (int b = 0; b < CB; ++b) acc[b] = mfma(a, bx[b][kk], acc[b]);
       }
-      const int h0 = 8 * ht + 2 * q;
-      const R b0r = bias[2 * h0], b0i = bias[2 * h0 + 1];
-      const R b1r = bias[2 * h0 + 2], b1i = bias[2 * h0 + 3];
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
         R tv[4];
+        const R ax0 = logcosh_step<R, WANT_T>((R)acc[b][0], (R)acc[b][1], pr[b], pi[b], par[b],
+                                              tv[0], tv[1]);
+        const R ax1 = logcosh_step<R, WANT_T>((R)acc[b][2], (R)acc[b][3], pr[b], pi[b], par[b],
+                                              tv[2], tv[3]);
+        sax[b] += (double)(ax0 + ax1);
+        if constexpr (WANT_T) {
+          if (live[b]) {
+            R* dst = t_out + ((((size_t)s_of[b] * n_htiles + ht) * G + g_of[b]) * 8 + 2 * q) * 2;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const R x = (R)acc[b][2 * u] + (u ? b1r : b0r);
-          const R y = (R)acc[b][2 * u + 1] + (u ? b1i : b0i);
-          if (t_out)
-            logcosh_step<R, true>(x, y, pr[b], pi[b], sax[b], tv[2 * u], tv[2 * u + 1]);
-          else
-            logcosh_step<R, false>(x, y, pr[b], pi[b], sax[b], tv[2 * u], tv[2 * u + 1]);
-        }
-        if (t_out && live[b]) {
-          R* dst = t_out + ((((size_t)s_of[b] * n_htiles + ht) * G + g_of[b]) * 8 + 2 * q) * 2;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) dst[v] = tv[v];
+            for (int v = 0; v < 4; ++v) dst[v] = tv[v];
+          }
         }
       }
       if ((tt & 7) == 7) {
@@ -103,45 +112,73 @@ __global__ __launch_bounds__(256) void theta_kernel(
         for (int b = 0; b < CB; ++b) renorm(pr[b], pi[b], pe[b]);
       }
     }
-    // combine the four lane groups holding different hidden units of one image
+
+    // a . (g sigma), per lane over its sites, for every column block
+    R axr[CB], axi[CB];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) axr[b] = axi[b] = R(0);
+    const R* ak = avec + (size_t)k * N * 2;
+    if constexpr (PREC != NQS_BF16X2) {
+#pragma unroll
+      for (int kk = 0; kk < NK; ++kk) {
+        const R ar = ak[2 * (4 * kk + q)], ai = ak[2 * (4 * kk + q) + 1];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+          axr[b] = fmaf_t(bx[b][kk], ar, axr[b]);
+          axi[b] = fmaf_t(bx[b][kk], ai, axi[b]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const int8_t* srow = spins + s_of[b] * N;
+        const uint8_t* prow = perm + (size_t)g_of[b] * N;
+        for (int j = q; j < N; j += 4) {
+          const R xj = R(0.5) * (R)srow[prow[j]];
+          axr[b] = fmaf_t(xj, ak[2 * j], axr[b]);
+          axi[b] = fmaf_t(xj, ak[2 * j + 1], axi[b]);
+        }
+      }
+    }
+
+    // join the four lane groups; lane group q keeps column block q mod CB
+    double Lre = 0.0, Lim = 0.0, Ps = 1.0, Qs = 0.0;
+    int64_t s_sel = 0;
+    int g_sel = 0;
+    bool live_sel = false;
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
+      renorm(pr[b], pi[b], pe[b]);
+      apply_parity(pr[b], pi[b], par[b]);
       double Pr = (double)pr[b], Pi = (double)pi[b];
       int E = pe[b];
       double sx = sax[b];
+      R xr = axr[b], xi = axi[b];
 #pragma unroll
       for (int o = 16; o <= 32; o <<= 1) {
         const double orr = __shfl_xor(Pr, o, 64), oi = __shfl_xor(Pi, o, 64);
-        const int oe = __shfl_xor(E, o, 64);
-        const double os = __shfl_xor(sx, o, 64);
         const double nr = Pr * orr - Pi * oi;
         Pi = Pr * oi + Pi * orr;
         Pr = nr;
-        E += oe;
-        sx += os;
+        E += __shfl_xor(E, o, 64);
+        sx += __shfl_xor(sx, o, 64);
+        xr += __shfl_xor(xr, o, 64);
+        xi += __shfl_xor(xi, o, 64);
       }
-      // a . (g sigma): sites j = q (mod 4) per lane, then reduce over q
-      double axr = 0.0, axi = 0.0;
-      const int8_t* srow = spins + s_of[b] * N;
-      const uint8_t* prow = perm + (size_t)g_of[b] * N;
-      const R* ak = avec + (size_t)k * N * 2;
-      for (int j = q; j < N; j += 4) {
-        const double xj = 0.5 * (double)srow[prow[j]];
-        axr += xj * (double)ak[2 * j];
-        axi += xj * (double)ak[2 * j + 1];
+      if ((q & (CB - 1)) == b) {
+        Lre = (double)xr + sx + (double)E * 0.69314718055994530942;
+        Lim = (double)xi;
+        Ps = Pr;
+        Qs = Pi;
+        s_sel = s_of[b];
+        g_sel = g_of[b];
+        live_sel = live[b];
       }
-      axr += __shfl_xor(axr, 16, 64);
-      axi += __shfl_xor(axi, 16, 64);
-      axr += __shfl_xor(axr, 32, 64);
-      axi += __shfl_xor(axi, 32, 64);
-      if (q == 0 && live[b]) {
-        const double mag = sqrt(Pr * Pr + Pi * Pi);
-        const double lre = axr + sx + log(mag) + (double)E * 0.69314718055994530942;
-        const double lim = axi + atan2(Pi, Pr);
-        double* o = Lout + (((size_t)s_of[b] * K + k) * G + g_of[b]) * 2;
-        o[0] = lre;
-        o[1] = lim;
-      }
+    }
+    if (q < CB && live_sel) {
+      double* o = Lout + (((size_t)s_sel * K + k) * G + g_sel) * 2;
+      o[0] = Lre + log(sqrt(Ps * Ps + Qs * Qs));
+      o[1] = Lim + atan2(Qs, Ps);
     }
   }
 }
@@ -209,9 +246,14 @@ hipError_t theta_for(const nqs_ctx* c, const int8_t* spins, int64_t S, double* L
   const int64_t total_cb = S * (c->G / 16);
   const int64_t waves = (total_cb + CB - 1) / CB;
   const int64_t blocks = (waves + 3) / 4;
-  theta_kernel<N, PREC, CB><<<(unsigned)blocks, 256, 0, st>>>(
-      spins, S, c->dev.perm, c->G, (const typename T::AFrag*)c->par.wfrag,
-      (const R*)c->par.bias, (const R*)c->par.avec, c->K, c->M, c->n_htiles, Lout, (R*)t_out);
+  if (t_out)
+    theta_kernel<N, PREC, CB, true><<<(unsigned)blocks, 256, 0, st>>>(
+        spins, S, c->dev.perm, c->G, (const typename T::AFrag*)c->par.wfrag,
+        (const R*)c->par.bias, (const R*)c->par.avec, c->K, c->M, c->n_htiles, Lout, (R*)t_out);
+  else
+    theta_kernel<N, PREC, CB, false><<<(unsigned)blocks, 256, 0, st>>>(
+        spins, S, c->dev.perm, c->G, (const typename T::AFrag*)c->par.wfrag,
+        (const R*)c->par.bias, (const R*)c->par.avec, c->K, c->M, c->n_htiles, Lout, nullptr);
   return hipGetLastError();
 }
 

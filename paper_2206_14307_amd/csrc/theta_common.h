@@ -42,33 +42,44 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// Working-precision transcendentals.  FP64 uses the accurate library forms.
-// FP32 uses the hardware exp2 / log2 / rcp instructions and the sincos below:
-// Cody-Waite reduction y = k pi/2 + r, |r| <= pi/4 (pi/2 split into an exact
-// float head and a tail), then the Taylor series of sin to r^9 and of cos to
-// r^10, whose truncation errors are below 3e-9 on |r| <= pi/4; the quadrant
-// k mod 4 rotates (sin r, cos r).  It is accurate to a few ulp for the
-// moderate arguments of Im(theta) and, unlike a table-driven library form,
-// keeps register pressure low inside the fused kernels.
+// Working-precision transcendentals.  FP64 uses the accurate library forms;
+// FP32 uses the hardware exp2 / log2 / rcp instructions and the sine and
+// cosine below.
+//
+// sincos_pi: Cody-Waite reduction by multiples of pi (pi split into the float
+// nearest to it and the remainder), y = k pi + r with |r| <= pi/2, then
+// sin r = r + r^3 P(r^2) and cos r = 1 + r^2 Q(r^2) with near-minimax P, Q
+// fitted on [-pi/2, pi/2] (gen_sincos_coeffs.py; approximation errors 1.7e-8
+// and 5e-9, below FP32 rounding).  It returns sin r and cos r, which are
+// (-1)^k sin y and (-1)^k cos y; bit 0 of par is toggled by k.  k is rounded
+// by adding 1.5 * 2^23, which leaves it in the low mantissa bits, so its
+// parity costs one XOR.
 __device__ __forceinline__ double exp_t(double v) { return exp(v); }
 __device__ __forceinline__ float exp_t(float v) { return __expf(v); }
+__device__ __forceinline__ void sincos_pi(float y, float& sn, float& cs, uint32_t& par) {
+  const float t = fmaf(y, 0.318309886183790672f, 12582912.0f);   // 1/pi, 1.5 * 2^23
+  const float kf = t - 12582912.0f;
+  float r = fmaf(-kf, 3.14159274101257324f, y);                   // float(pi)
+  r = fmaf(-kf, -8.742278013e-8f, r);                             // pi - float(pi)
+  par ^= __float_as_uint(t);
+  const float z = r * r;
+  const float p = fmaf(fmaf(fmaf(2.600053676e-6f, z, -1.980661473e-4f), z, 8.333017118e-3f), z,
+                       -1.666665673e-1f);
+  sn = fmaf(r * z, p, r);
+  const float qq = fmaf(fmaf(fmaf(fmaf(-2.607709746e-7f, z, 2.476188638e-5f), z,
+                                  -1.388840377e-3f), z, 4.166664183e-2f), z, -0.5f);
+  cs = fmaf(z, qq, 1.0f);
+}
+__device__ __forceinline__ void sincos_pi(double y, double& sn, double& cs, uint32_t&) {
+  sincos(y, &sn, &cs);
+}
 __device__ __forceinline__ void sincos_t(double v, double* s, double* c) { sincos(v, s, c); }
 __device__ __forceinline__ void sincos_t(float v, float* s, float* c) {
-  const float k = rintf(v * 0.636619772367581343f);             // 2/pi
-  float r = fmaf(-k, 1.57079637050628662109375f, v);            // float(pi/2)
-  r = fmaf(-k, -4.37113900018624283e-8f, r);                    // pi/2 - float(pi/2)
-  const float r2 = r * r;
-  const float sp = fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, 2.75573192e-6f, -1.98412698e-4f),
-                                          8.33333333e-3f), -1.66666667e-1f), 0.0f);
-  const float sn = fmaf(r, sp, r);
-  const float cs = fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -2.75573192e-7f, 2.48015873e-5f),
-                                                   -1.38888889e-3f), 4.16666667e-2f), -0.5f),
-                        1.0f);
-  const int qd = ((int)k) & 3;
-  const float s0 = (qd & 1) ? cs : sn;
-  const float c0 = (qd & 1) ? sn : cs;
-  *s = (qd & 2) ? -s0 : s0;
-  *c = ((qd + 1) & 2) ? -c0 : c0;
+  uint32_t par = 0;
+  float sn, cs;
+  sincos_pi(v, sn, cs, par);
+  *s = (par & 1u) ? -sn : sn;
+  *c = (par & 1u) ? -cs : cs;
 }
 __device__ __forceinline__ double rcp_t(double v) { return 1.0 / v; }
 // hardware reciprocal (1 ulp)
@@ -103,29 +114,40 @@ __device__ __forceinline__ void load_bfrag(const int8_t* srow, const uint8_t* pr
   }
 }
 
-// One hidden unit of the epilogue: with x = Re theta, y = Im theta,
-// e = exp(-2|x|), c = (1+e) cos y + i sgn(x)(1-e) sin y = 2cosh(theta) e^{-|x|};
-// multiplies c into (pr, pi), adds |x| to sax and, if wanted, returns
-// tanh(theta) = (sgn(x)(1-e^2) + i 4 e sin y cos y) / |c|^2.
+// One hidden unit of the epilogue.  With x = Re theta, y = Im theta = k pi + r
+// and e = exp(-2|x|):
+//   2 cosh(theta) = e^{|x|} (-1)^k c,  c = (1+e) cos r + i sgn(x) (1-e) sin r,
+//   tanh(theta)   = (sgn(x)(1-e^2) + i 4 e sin r cos r) / |c|^2
+// (both terms of e^{theta} + e^{-theta} change sign together when y moves by
+// pi, and tanh has period i pi).  Multiplies c into (pr, pi), toggles bit 0 of
+// par by k, returns |x| and, if wanted, tanh(theta).
 template <typename R, bool WANT_T>
-__device__ __forceinline__ void logcosh_step(R x, R y, R& pr, R& pi, double& sax, R& tr, R& ti) {
-  const R ax = x < R(0) ? -x : x;
-  const R sg = x < R(0) ? R(-1) : R(1);
+__device__ __forceinline__ R logcosh_step(R x, R y, R& pr, R& pi, uint32_t& par, R& tr, R& ti) {
+  const R ax = fabs(x);
   const R e = exp_t(R(-2) * ax);
-  R sy, cy;
-  sincos_t(y, &sy, &cy);
-  const R cr = (R(1) + e) * cy;
-  const R ci = sg * (R(1) - e) * sy;
-  const R nr = pr * cr - pi * ci;
-  pi = pr * ci + pi * cr;
+  R sn, cs;
+  sincos_pi(y, sn, cs, par);
+  const R cr = fmaf_t(e, cs, cs);
+  const R cu = fmaf_t(-e, sn, sn);
+  const R ci = x < R(0) ? -cu : cu;
+  const R nr = fmaf_t(pr, cr, -(pi * ci));
+  pi = fmaf_t(pr, ci, pi * cr);
   pr = nr;
-  sax += (double)ax;
   if constexpr (WANT_T) {
-    const R d = fmaf_t(R(2) * e, cy * cy - sy * sy, fmaf_t(e, e, R(1)));
+    const R d = fmaf_t(e + e, fmaf_t(cs, cs, -(sn * sn)), fmaf_t(e, e, R(1)));
     const R inv = rcp_t(d);
-    tr = sg * (R(1) - e * e) * inv;
-    ti = R(4) * e * sy * cy * inv;
+    const R tu = fmaf_t(-e, e, R(1)) * inv;
+    tr = x < R(0) ? -tu : tu;
+    ti = (R(4) * e) * (sn * cs) * inv;
   }
+  return ax;
+}
+
+// Apply the collected (-1)^k of the epilogue to a product.
+template <typename R>
+__device__ __forceinline__ void apply_parity(R& pr, R& pi, uint32_t par) {
+  pr = (par & 1u) ? -pr : pr;
+  pi = (par & 1u) ? -pi : pi;
 }
 
 // Keep a running complex product in range: scale by a power of two.
