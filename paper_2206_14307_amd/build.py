@@ -35,7 +35,10 @@ def _flags(src):
     if src.endswith(".hip"):
         return common + [f"--offload-arch={ARCH}", "-x", "hip",
                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                         "-munsafe-fp-atomics"]
+                         "-munsafe-fp-atomics",
+                         # MFMA accumulators in ordinary VGPRs: the epilogues read every
+                         # result, and AGPR accumulators cost a copy per register
+                         "-mllvm", "-amdgpu-mfma-vgpr-form"]
     return common + ["-D__HIP_PLATFORM_AMD__"]
 
 

@@ -54,6 +54,49 @@ __device__ __forceinline__ void mul_one_plus(R& pr, R& pi, R tr, R ti, R Tr, R T
   pi = ni;
 }
 
+// Row swaps of gfx950 (a row is 16 lanes; rows 0..3 are q = 0..3):
+// swap16(x, y): x <- [x0 y0 x2 y2], y <- [x1 y1 x3 y3];
+// swap32(x, y): x <- [x0 x1 y0 y1], y <- [x2 x3 y2 y3].
+__device__ __forceinline__ void swap16(float& x, float& y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap32(float& x, float& y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap16(double& x, double& y) {
+  const unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)bx, (unsigned)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(bx >> 32), (unsigned)(by >> 32),
+                                                   false, false);
+  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ void swap32(double& x, double& y) {
+  const unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32),
+                                                   false, false);
+  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
+__device__ __forceinline__ void swap16(int& x, int& y) {
+  const auto r = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)y, false, false);
+  x = (int)r[0];
+  y = (int)r[1];
+}
+__device__ __forceinline__ void swap32(int& x, int& y) {
+  const auto r = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)y, false, false);
+  x = (int)r[0];
+  y = (int)r[1];
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -91,38 +91,6 @@ __device__ __forceinline__ void step_rc(R& pr, R& pi, R s, R tr, R ti, R Ur, R U
   pr = nr;
 }
 
-// Row swaps of gfx950 (a row is 16 lanes; rows 0..3 are q = 0..3):
-// swap16(x, y): x <- [x0 y0 x2 y2], y <- [x1 y1 x3 y3];
-// swap32(x, y): x <- [x0 x1 y0 y1], y <- [x2 x3 y2 y3].
-__device__ __forceinline__ void swap16(float& x, float& y) {
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false,
-                                                  false);
-  x = __uint_as_float(r[0]);
-  y = __uint_as_float(r[1]);
-}
-__device__ __forceinline__ void swap32(float& x, float& y) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
-                                                  false);
-  x = __uint_as_float(r[0]);
-  y = __uint_as_float(r[1]);
-}
-__device__ __forceinline__ void swap16(double& x, double& y) {
-  const unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
-  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)bx, (unsigned)by, false, false);
-  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(bx >> 32), (unsigned)(by >> 32),
-                                                   false, false);
-  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
-  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
-}
-__device__ __forceinline__ void swap32(double& x, double& y) {
-  const unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
-  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32),
-                                                   false, false);
-  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
-  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
-}
-
 // Complex products over the four q rows of two bonds at once: on entry p
 // holds bond 0's and o bond 1's per-row partial products; on exit p holds the
 // full product of bond 0 in rows 0, 2 and of bond 1 in rows 1, 3.

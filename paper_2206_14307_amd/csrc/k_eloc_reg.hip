@@ -214,20 +214,6 @@ __device__ __forceinline__ int ilogb_bits(double v) {
 __device__ __forceinline__ float rcp_fast(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ double rcp_fast(double v) { return 1.0 / v; }
 
-__device__ __forceinline__ void swap32(float& x, float& y) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
-                                                  false);
-  x = __uint_as_float(r[0]);
-  y = __uint_as_float(r[1]);
-}
-__device__ __forceinline__ void swap32(double& x, double& y) {
-  const unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
-  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32),
-                                                   false, false);
-  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
-  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
-}
 // (x of lanes 0..31) * (x of lanes 32..63), in every lane
 template <typename R>
 __device__ __forceinline__ void join_halves(R& xr, R& xi) {

@@ -35,8 +35,10 @@ struct GradCfg {
   static constexpr int NST = (N + 1 + 15) / 16;  // site tiles incl. the ones row
   static constexpr int NK = nk_of<N, PREC>();
   static constexpr int TS = 16 * 17;             // one padded 16 x 16 transpose tile
+  static constexpr int XS = 16 * NST;            // row of the image tile: sites + ones + zeros
   static constexpr size_t LDS = (size_t)NHT * NK * 64 * sizeof(typename T::AFrag) +
                                 (size_t)kGradWaves * NCT * TS * sizeof(float) +
+                                (size_t)kGradWaves * 16 * XS * sizeof(float) +
                                 (size_t)(2 * KM + 2 * K * N) * sizeof(float);
 };
 
@@ -56,9 +58,11 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
   using T = ThetaTraits<PREC>;
   using AF = typename T::AFrag;
   constexpr int NHT = Cfg::NHT, NCT = Cfg::NCT, NST = Cfg::NST, NK = Cfg::NK, TS = Cfg::TS;
+  constexpr int XS = Cfg::XS;
   constexpr int TPR = M / 8;
   __shared__ __align__(16) AF Wl[NHT * NK * 64];
   __shared__ float tb[kGradWaves][NCT * TS];
+  __shared__ float xb[kGradWaves][16 * XS];          // the block's images x_g (rows), sites (columns)
   __shared__ float bl[2 * Cfg::KM], al[2 * K * N];   // hidden and visible biases
 
   for (int idx = threadIdx.x; idx < NHT * NK * 64; idx += blockDim.x) Wl[idx] = wfrag[idx];
@@ -67,6 +71,9 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
   const int lane0 = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float* tw = tb[wv];
   for (int idx = lane0; idx < TS; idx += 64) tw[NHT * TS + idx] = 0.f;   // unused u columns
+  float* xw = xb[wv];
+  for (int idx = lane0; idx < 16 * (XS - N); idx += 64)                   // ones row, zero pad
+    xw[(idx / (XS - N)) * XS + N + idx % (XS - N)] = idx % (XS - N) == 0 ? 1.f : 0.f;
   __syncthreads();
 
   const int nblk = G / 16;
@@ -90,6 +97,19 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
       const uint8_t* prow = perm + (size_t)g * N;
       typename T::BFrag bx[NK];
       load_bfrag<N, PREC>(srow, prow, q, bx);
+      // the images as rows of the contraction's A operand (sites x images)
+      if constexpr (PREC == NQS_BF16X2) {
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int kap = 32 * kk + 8 * q + e;
+            if (kap < N) xw[c * XS + kap] = (float)bx[kk][e];
+          }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) xw[c * XS + 4 * kk + q] = (float)bx[kk];
+      }
       float tr[NHT * 2], ti[NHT * 2], Pr[K], Pi[K], Ai[K];
       double Er[K];
       theta_block<N, PREC, K, M>(Wl, bx, bl, al, srow, prow, lane, tr, ti, Er, Pr, Pi, Ai);
@@ -139,16 +159,12 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
       }
       wave_sync_lds();
       // contraction over the block's images, 4 per MFMA step: images 4r + q
+      const float* xl = xw + q * XS + c;
 #pragma unroll 1
       for (int r = 0; r < 4; ++r) {
-        const int gA = blk * 16 + 4 * r + q;
-        const uint8_t* pa = perm + (size_t)gA * N;
         float a[NST];
 #pragma unroll
-        for (int st = 0; st < NST; ++st) {
-          const int j = 16 * st + c;
-          a[st] = j < N ? 0.5f * (float)srow[pa[j]] : (j == N ? 1.f : 0.f);
-        }
+        for (int st = 0; st < NST; ++st) a[st] = xl[4 * r * XS + 16 * st];
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) {
           const float b = tw[ct * TS + (4 * r + q) * 17 + c];

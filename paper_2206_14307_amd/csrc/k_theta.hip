@@ -30,6 +30,117 @@ namespace nqs {
 
 namespace {
 
+// W fragments and biases of hidden tile ht for this lane.
+template <int PREC, int NK>
+__device__ __forceinline__ void load_tile(typename ThetaTraits<PREC>::AFrag (&wf)[NK],
+                                          typename ThetaTraits<PREC>::Acc& b0,
+                                          const typename ThetaTraits<PREC>::AFrag* wfrag,
+                                          const typename ThetaTraits<PREC>::R* bias, int ht,
+                                          int lane, int q) {
+  const typename ThetaTraits<PREC>::AFrag* ap = wfrag + (size_t)ht * NK * 64 + lane;
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk) wf[kk] = ap[kk * 64];
+  const int h0 = 8 * ht + 2 * q;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) b0[v] = bias[2 * h0 + v];
+}
+
+// theta of one hidden tile for the CB column blocks: accumulators start from
+// the biases.
+template <int PREC, int CB, int NK>
+__device__ __forceinline__ void mfma_tile(typename ThetaTraits<PREC>::Acc (&acc)[CB],
+                                          const typename ThetaTraits<PREC>::AFrag (&wf)[NK],
+                                          const typename ThetaTraits<PREC>::Acc& b0,
+                                          const typename ThetaTraits<PREC>::BFrag (&bx)[CB][NK]) {
+#pragma unroll
+  for (int b = 0; b < CB; ++b) acc[b] = b0;
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+    for (int b = 0; b < CB; ++b) acc[b] = mfma(wf[kk], bx[b][kk], acc[b]);
+}
+
+// Epilogue of one hidden tile (two units per lane and column block).
+template <int PREC, int CB, bool WANT_T>
+__device__ __forceinline__ void epi_tile(const typename ThetaTraits<PREC>::Acc (&acc)[CB],
+                                              typename ThetaTraits<PREC>::R (&pr)[CB],
+                                              typename ThetaTraits<PREC>::R (&pi)[CB],
+                                              uint32_t (&par)[CB], double (&sax)[CB],
+                                              typename ThetaTraits<PREC>::R* t_out,
+                                              const int64_t (&s_of)[CB], const int (&g_of)[CB],
+                                              const bool (&live)[CB], int ht, int n_htiles,
+                                              int G, int q) {
+  using R = typename ThetaTraits<PREC>::R;
+#pragma unroll
+  for (int b = 0; b < CB; ++b) {
+    R tv[4];
+    const R ax0 = logcosh_step<R, WANT_T>((R)acc[b][0], (R)acc[b][1], pr[b], pi[b],
+                                                  par[b], tv[0], tv[1]);
+    const R ax1 = logcosh_step<R, WANT_T>((R)acc[b][2], (R)acc[b][3], pr[b], pi[b],
+                                                  par[b], tv[2], tv[3]);
+    sax[b] += (double)(ax0 + ax1);
+    if constexpr (WANT_T) {
+      if (live[b]) {
+        R* dst = t_out + ((((size_t)s_of[b] * n_htiles + ht) * G + g_of[b]) * 8 + 2 * q) * 2;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[v] = tv[v];
+      }
+    }
+  }
+}
+
+// Rows q = lane / 16 hold v[b] for the column blocks b < CB (CB = 4 or 2); on
+// exit row q holds the combination over all four rows of v[q mod CB].  Two
+// row swaps (v_permlane16_swap, v_permlane32_swap) serve all column blocks.
+template <int CB, typename V, typename Op>
+__device__ __forceinline__ V join_rows(const V (&v)[CB], Op op) {
+  V x0 = v[0], y0 = v[1];
+  swap16(x0, y0);
+  V a = op(x0, y0);
+  if constexpr (CB == 4) {
+    V x1 = v[2], y1 = v[3];
+    swap16(x1, y1);
+    V bb = op(x1, y1);
+    swap32(a, bb);
+    return op(a, bb);
+  } else {
+    V bb = a;
+    swap32(a, bb);
+    return op(a, bb);
+  }
+}
+// The same for complex products.
+template <int CB, typename R>
+__device__ __forceinline__ void join_rows_cmul(const R (&vr)[CB], const R (&vi)[CB], R& outr,
+                                               R& outi) {
+  auto cm = [](R& ar, R& ai, R br, R bi) {
+    const R nr = ar * br - ai * bi;
+    ai = ar * bi + ai * br;
+    ar = nr;
+  };
+  R xr = vr[0], yr = vr[1], xi = vi[0], yi = vi[1];
+  swap16(xr, yr);
+  swap16(xi, yi);
+  cm(xr, xi, yr, yi);
+  R br, bi;
+  if constexpr (CB == 4) {
+    R ur = vr[2], wr = vr[3], ui = vi[2], wi = vi[3];
+    swap16(ur, wr);
+    swap16(ui, wi);
+    cm(ur, ui, wr, wi);
+    br = ur;
+    bi = ui;
+  } else {
+    br = xr;
+    bi = xi;
+  }
+  swap32(xr, br);
+  swap32(xi, bi);
+  cm(xr, xi, br, bi);
+  outr = xr;
+  outi = xi;
+}
+
 template <int N, int PREC, int CB, bool WANT_T>
 __global__ __launch_bounds__(256) void theta_kernel(
     const int8_t* __restrict__ spins, int64_t S, const uint8_t* __restrict__ perm, int G,
@@ -42,24 +153,33 @@ __global__ __launch_bounds__(256) void theta_kernel(
   constexpr int NK = nk_of<N, PREC>();
   const int lane = threadIdx.x & 63;
   const int q = lane >> 4, c = lane & 15;
-  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  // column blocks wave*CB .. wave*CB + CB - 1 (wave-uniform; one division)
+  const int64_t wave =
+      (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int cb_per_s = G / 16;
   const int64_t total_cb = S * cb_per_s;
+  if (wave * CB >= total_cb) return;
 
   typename T::BFrag bx[CB][NK];
+  SpinBits sb[CB];
   int64_t s_of[CB];
   int g_of[CB];
   bool live[CB];
+  {
+    int64_t sc = (wave * CB) / cb_per_s;
+    int gb = (int)(wave * CB - sc * cb_per_s);
 #pragma unroll
-  for (int b = 0; b < CB; ++b) {
-    const int64_t cbi = wave * CB + b;
-    live[b] = cbi < total_cb;
-    const int64_t cbc = live[b] ? cbi : 0;
-    s_of[b] = cbc / cb_per_s;
-    g_of[b] = (int)(cbc % cb_per_s) * 16 + c;
-    load_bfrag<N, PREC>(spins + s_of[b] * N, perm + (size_t)g_of[b] * N, q, bx[b]);
+    for (int b = 0; b < CB; ++b) {
+      live[b] = wave * CB + b < total_cb;
+      s_of[b] = live[b] ? sc : 0;
+      g_of[b] = (live[b] ? gb : 0) * 16 + c;
+      sb[b] = load_bfrag<N, PREC>(spins + s_of[b] * N, perm + (size_t)g_of[b] * N, q, bx[b]);
+      if (++gb == cb_per_s) {
+        gb = 0;
+        ++sc;
+      }
+    }
   }
-  if (!live[0]) return;  // whole wave idle (live[0] is wave-uniform)
 
   const int tiles_per_rbm = M / 8;
   for (int k = 0; k < K; ++k) {
@@ -75,41 +195,62 @@ __global__ __launch_bounds__(256) void theta_kernel(
       par[b] = 0u;
       sax[b] = 0.0;
     }
-    for (int tt = 0; tt < tiles_per_rbm; ++tt) {
-      const int ht = k * tiles_per_rbm + tt;
-      const int h0 = 8 * ht + 2 * q;
-      typename T::Acc b0;
+    // Larger lattices (N > 36, longer MFMA chains per tile) software-pipeline
+    // the tile loop: the next tile's MFMAs and fragment loads are issued before
+    // the current epilogue.  At N <= 36 the plain loop, with fewer live
+    // registers, is faster.
+    if constexpr (N <= 36) {
+      for (int tt = 0; tt < tiles_per_rbm; ++tt) {
+        const int ht = k * tiles_per_rbm + tt;
+        typename T::AFrag wf[NK];
+        typename T::Acc b0, acc[CB];
+        load_tile<PREC, NK>(wf, b0, wfrag, bias, ht, lane, q);
+        mfma_tile<PREC, CB, NK>(acc, wf, b0, bx);
+        epi_tile<PREC, CB, WANT_T>(acc, pr, pi, par, sax, t_out, s_of, g_of, live, ht, n_htiles,
+                                   G, q);
+        if ((tt & 7) == 7) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) b0[v] = bias[2 * h0 + v];
-      typename T::Acc acc[CB];
-#pragma unroll
-      for (int b = 0; b < CB; ++b) acc[b] = b0;
-      const typename T::AFrag* ap = wfrag + (size_t)ht * NK * 64 + lane;
-#pragma unroll
-      for (int kk = 0; kk < NK; ++kk) {
-        const typename T::AFrag a = ap[kk * 64];
-#pragma unroll
-        for (int b = 0; b < CB; ++b) acc[b] = mfma(a, bx[b][kk], acc[b]);
-      }
-#pragma unroll
-      for (int b = 0; b < CB; ++b) {
-        R tv[4];
-        const R ax0 = logcosh_step<R, WANT_T>((R)acc[b][0], (R)acc[b][1], pr[b], pi[b], par[b],
-                                              tv[0], tv[1]);
-        const R ax1 = logcosh_step<R, WANT_T>((R)acc[b][2], (R)acc[b][3], pr[b], pi[b], par[b],
-                                              tv[2], tv[3]);
-        sax[b] += (double)(ax0 + ax1);
-        if constexpr (WANT_T) {
-          if (live[b]) {
-            R* dst = t_out + ((((size_t)s_of[b] * n_htiles + ht) * G + g_of[b]) * 8 + 2 * q) * 2;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) dst[v] = tv[v];
-          }
+          for (int b = 0; b < CB; ++b) renorm(pr[b], pi[b], pe[b]);
         }
       }
-      if ((tt & 7) == 7) {
-#pragma unroll
-        for (int b = 0; b < CB; ++b) renorm(pr[b], pi[b], pe[b]);
+    } else {
+      // Software pipeline over the RBM's hidden tiles: the MFMAs of tile tt+1
+      // are issued (into the other accumulator set) before the epilogue of tile
+      // tt, and the fragments of tile tt+2 are loaded meanwhile.  Buffers A / B
+      // alternate between even and odd tiles.
+      const int T0 = k * tiles_per_rbm, TL = T0 + tiles_per_rbm - 1;
+      typename T::AFrag wfA[NK], wfB[NK];
+      typename T::Acc bA, bB, accA[CB], accB[CB];
+      load_tile<PREC, NK>(wfA, bA, wfrag, bias, T0, lane, q);
+      load_tile<PREC, NK>(wfB, bB, wfrag, bias, min(T0 + 1, TL), lane, q);
+      mfma_tile<PREC, CB, NK>(accA, wfA, bA, bx);
+      load_tile<PREC, NK>(wfA, bA, wfrag, bias, min(T0 + 2, TL), lane, q);
+      int ht = T0;
+      for (; ht + 2 <= TL; ht += 2) {
+        mfma_tile<PREC, CB, NK>(accB, wfB, bB, bx);                       // tile ht+1
+        epi_tile<PREC, CB, WANT_T>(accA, pr, pi, par, sax, t_out, s_of, g_of, live, ht, n_htiles,
+                                   G, q);
+        load_tile<PREC, NK>(wfB, bB, wfrag, bias, min(ht + 3, TL), lane, q);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_tile<PREC, CB, NK>(accA, wfA, bA, bx);                       // tile ht+2
+        epi_tile<PREC, CB, WANT_T>(accB, pr, pi, par, sax, t_out, s_of, g_of, live, ht + 1,
+                                   n_htiles, G, q);
+        load_tile<PREC, NK>(wfA, bA, wfrag, bias, min(ht + 4, TL), lane, q);
+        __builtin_amdgcn_sched_barrier(0);
+        if (((ht - T0) & 7) == 6) {
+  #pragma unroll
+          for (int b = 0; b < CB; ++b) renorm(pr[b], pi[b], pe[b]);
+        }
+      }
+      if (ht + 1 <= TL) {
+        mfma_tile<PREC, CB, NK>(accB, wfB, bB, bx);
+        epi_tile<PREC, CB, WANT_T>(accA, pr, pi, par, sax, t_out, s_of, g_of, live, ht, n_htiles,
+                                   G, q);
+        epi_tile<PREC, CB, WANT_T>(accB, pr, pi, par, sax, t_out, s_of, g_of, live, ht + 1,
+                                   n_htiles, G, q);
+      } else {
+        epi_tile<PREC, CB, WANT_T>(accA, pr, pi, par, sax, t_out, s_of, g_of, live, ht, n_htiles,
+                                   G, q);
       }
     }
 
@@ -131,104 +272,105 @@ __global__ __launch_bounds__(256) void theta_kernel(
     } else {
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
-        const int8_t* srow = spins + s_of[b] * N;
         const uint8_t* prow = perm + (size_t)g_of[b] * N;
-        for (int j = q; j < N; j += 4) {
-          const R xj = R(0.5) * (R)srow[prow[j]];
-          axr[b] = fmaf_t(xj, ak[2 * j], axr[b]);
-          axi[b] = fmaf_t(xj, ak[2 * j + 1], axi[b]);
+#pragma unroll
+        for (int jj = 0; jj < (N + 3) / 4; ++jj) {
+          const int j = 4 * jj + q;
+          if (j < N) {
+            const R xj = __uint_as_float(x_bits<N>(sb[b], prow[j]));
+            axr[b] = fmaf_t(xj, ak[2 * j], axr[b]);
+            axi[b] = fmaf_t(xj, ak[2 * j + 1], axi[b]);
+          }
         }
       }
     }
 
     // join the four lane groups; lane group q keeps column block q mod CB
-    double Lre = 0.0, Lim = 0.0, Ps = 1.0, Qs = 0.0;
-    int64_t s_sel = 0;
-    int g_sel = 0;
-    bool live_sel = false;
+    R jpr[CB], jpi[CB];
+    int E[CB];
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
       renorm(pr[b], pi[b], pe[b]);
       apply_parity(pr[b], pi[b], par[b]);
-      double Pr = (double)pr[b], Pi = (double)pi[b];
-      int E = pe[b];
-      double sx = sax[b];
-      R xr = axr[b], xi = axi[b];
+      jpr[b] = pr[b];
+      jpi[b] = pi[b];
+      E[b] = pe[b];
+    }
+    R Pj, Qj;
+    join_rows_cmul<CB>(jpr, jpi, Pj, Qj);
+    const int Es = join_rows<CB>(E, [](int u, int v) { return u + v; });
+    const double sx = join_rows<CB>(sax, [](double u, double v) { return u + v; });
+    const R xr = join_rows<CB>(axr, [](R u, R v) { return u + v; });
+    const R xi = join_rows<CB>(axi, [](R u, R v) { return u + v; });
+    const int bs = q & (CB - 1);
+    int64_t s_sel = s_of[0];
+    int g_sel = g_of[0];
+    bool live_sel = live[0];
 #pragma unroll
-      for (int o = 16; o <= 32; o <<= 1) {
-        const double orr = __shfl_xor(Pr, o, 64), oi = __shfl_xor(Pi, o, 64);
-        const double nr = Pr * orr - Pi * oi;
-        Pi = Pr * oi + Pi * orr;
-        Pr = nr;
-        E += __shfl_xor(E, o, 64);
-        sx += __shfl_xor(sx, o, 64);
-        xr += __shfl_xor(xr, o, 64);
-        xi += __shfl_xor(xi, o, 64);
-      }
-      if ((q & (CB - 1)) == b) {
-        Lre = (double)xr + sx + (double)E * 0.69314718055994530942;
-        Lim = (double)xi;
-        Ps = Pr;
-        Qs = Pi;
+    for (int b = 1; b < CB; ++b)
+      if (bs == b) {
         s_sel = s_of[b];
         g_sel = g_of[b];
         live_sel = live[b];
       }
+    double Lre = (double)xr + sx, Lim = (double)xi;
+    const double Ps = (double)Pj, Qs = (double)Qj;
+    // log and arg of the joined product (FP32 precisions: of its mantissa in
+    // [1/2, 1), in FP32)
+    if constexpr (PREC == NQS_FP64) {
+      Lre += log(sqrt(Ps * Ps + Qs * Qs)) + (double)Es * 0.69314718055994530942;
+      Lim += atan2(Qs, Ps);
+    } else {
+      int ex = 0;
+      const double mx = fmax(fabs(Ps), fabs(Qs));
+      if (mx > 0.0) frexp(mx, &ex);
+      const float pm = (float)ldexp(Ps, -ex), qm = (float)ldexp(Qs, -ex);
+      const float lg = 0.5f * __log2f(fmaf(pm, pm, qm * qm));
+      Lre += ((double)lg + (double)(Es + ex)) * 0.69314718055994530942;
+      Lim += (double)atan2f(qm, pm);
     }
     if (q < CB && live_sel) {
       double* o = Lout + (((size_t)s_sel * K + k) * G + g_sel) * 2;
-      o[0] = Lre + log(sqrt(Ps * Ps + Qs * Qs));
-      o[1] = Lim + atan2(Qs, Ps);
+      o[0] = Lre;
+      o[1] = Lim;
     }
   }
 }
 
 // Per-sample log-sum-exp over (k, g): log psi = m + log sum chi_g exp(L - m);
 // the normalised image weights w = chi_g exp(L - log psi) feed E_loc and O_k.
+// One wavefront per sample (shuffle reductions, no barriers), FP64 throughout.
 template <typename R>
-__global__ __launch_bounds__(256) void lse_kernel(const double* __restrict__ L, int KG, int G,
-                                                  const double* __restrict__ chi,
+__global__ __launch_bounds__(256) void lse_kernel(const double* __restrict__ L, int64_t S, int KG,
+                                                  int G, const double* __restrict__ chi,
                                                   double* __restrict__ logpsi, R* __restrict__ w) {
-  const int64_t s = blockIdx.x;
+  const int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= S) return;
+  const int lane = threadIdx.x & 63;
   const double* Ls = L + (size_t)s * KG * 2;
-  __shared__ double red[2][4];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double m = -INFINITY;
-  for (int i = threadIdx.x; i < KG; i += blockDim.x) m = fmax(m, Ls[2 * i]);
+  for (int i = lane; i < KG; i += 64) m = fmax(m, Ls[2 * i]);
   m = wave_max(m);
-  if (lane == 0) red[0][wv] = m;
-  __syncthreads();
-  m = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
-  __syncthreads();
   double sr = 0.0, si = 0.0;
-  for (int i = threadIdx.x; i < KG; i += blockDim.x) {
-    const double ch = chi[i % G];
-    const double e = ch * exp(Ls[2 * i] - m);
+  for (int i = lane; i < KG; i += 64) {
+    const double e = chi[i % G] * exp(Ls[2 * i] - m);
     double sn, cs;
     sincos(Ls[2 * i + 1], &sn, &cs);
-    sr += e * cs;
-    si += e * sn;
+    sr = fma(e, cs, sr);
+    si = fma(e, sn, si);
   }
   sr = wave_sum(sr);
   si = wave_sum(si);
-  if (lane == 0) {
-    red[0][wv] = sr;
-    red[1][wv] = si;
-  }
-  __syncthreads();
-  sr = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-  si = red[1][0] + red[1][1] + red[1][2] + red[1][3];
   const double lre = m + 0.5 * log(sr * sr + si * si);
   const double lim = atan2(si, sr);
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     logpsi[2 * s] = lre;
     logpsi[2 * s + 1] = lim;
   }
   if (w) {
     R* ws = w + (size_t)s * KG * 2;
-    for (int i = threadIdx.x; i < KG; i += blockDim.x) {
-      const double ch = chi[i % G];
-      const double e = ch * exp(Ls[2 * i] - lre);
+    for (int i = lane; i < KG; i += 64) {
+      const double e = chi[i % G] * exp(Ls[2 * i] - lre);
       double sn, cs;
       sincos(Ls[2 * i + 1] - lim, &sn, &cs);
       ws[2 * i] = (R)(e * cs);
@@ -242,7 +384,9 @@ hipError_t theta_for(const nqs_ctx* c, const int8_t* spins, int64_t S, double* L
                      hipStream_t st) {
   using T = ThetaTraits<PREC>;
   using R = typename T::R;
-  constexpr int CB = N <= 36 ? 4 : 2;
+  // column blocks per wave: 4 for FP32 / FP64 at N <= 36, otherwise 2 (fewer
+  // live registers where the fragments or the MFMA chains are longer)
+  constexpr int CB = (N <= 36 && PREC != NQS_BF16X2) ? 4 : 2;
   const int64_t total_cb = S * (c->G / 16);
   const int64_t waves = (total_cb + CB - 1) / CB;
   const int64_t blocks = (waves + 3) / 4;
@@ -282,12 +426,13 @@ hipError_t launch_theta(const nqs_ctx* c, const int8_t* spins, int64_t S, double
 hipError_t launch_lse(const nqs_ctx* c, const double* L, int64_t S, double* logpsi_out,
                       void* w_out, hipStream_t st) {
   if (S <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((S + 3) / 4);
   if (c->prec == NQS_FP64)
-    lse_kernel<double><<<(unsigned)S, 256, 0, st>>>(L, c->K * c->G, c->G, c->dev.chi, logpsi_out,
-                                                    (double*)w_out);
+    lse_kernel<double><<<blocks, 256, 0, st>>>(L, S, c->K * c->G, c->G, c->dev.chi, logpsi_out,
+                                               (double*)w_out);
   else
-    lse_kernel<float><<<(unsigned)S, 256, 0, st>>>(L, c->K * c->G, c->G, c->dev.chi, logpsi_out,
-                                                   (float*)w_out);
+    lse_kernel<float><<<blocks, 256, 0, st>>>(L, S, c->K * c->G, c->G, c->dev.chi, logpsi_out,
+                                              (float*)w_out);
   return hipGetLastError();
 }
 

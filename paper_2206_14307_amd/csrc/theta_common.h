@@ -89,29 +89,61 @@ __device__ __forceinline__ float log_t(float v) { return __logf(v); }
 __device__ __forceinline__ double atan2_t(double y, double x) { return atan2(y, x); }
 __device__ __forceinline__ float atan2_t(float y, float x) { return atan2f(y, x); }
 
-// Build the B-operand fragments of one 16-image column block.
+// Down spins of one configuration as bit masks (bit j set: spin j is down),
+// from a vote of the wavefront's lanes over the spin row; x_j = -+1/2 of a
+// gathered image is then a shift of the mask.  All 64 lanes must be active.
+struct SpinBits {
+  uint64_t lo, hi;
+};
+template <int N>
+__device__ __forceinline__ SpinBits spin_bits(const int8_t* srow) {
+  const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+  SpinBits m;
+  m.lo = __builtin_amdgcn_ballot_w64(lane < N && srow[lane] < 0);
+  m.hi = N > 64 ? __builtin_amdgcn_ballot_w64(lane + 64 < N && srow[lane + 64] < 0) : 0ull;
+  return m;
+}
+// FP32 bit pattern of x = +1/2 (spin up) or -1/2 (down) at site p.
+template <int N>
+__device__ __forceinline__ uint32_t x_bits(const SpinBits& m, int p) {
+  if constexpr (N <= 64) {
+    return 0x3F000000u | ((uint32_t)(m.lo >> p) << 31);
+  } else {
+    const uint64_t w = p < 64 ? m.lo : m.hi;
+    return 0x3F000000u | ((uint32_t)(w >> (p & 63)) << 31);
+  }
+}
+
+// Build the B-operand fragments of one 16-image column block: lane (q, c)
+// holds sites 4 kk + q of image c (FP32 / FP64), or for split BF16 the K
+// positions 32 kk + 8 q + e of [x | x | 0].
 template <int N, int PREC>
-__device__ __forceinline__ void load_bfrag(const int8_t* srow, const uint8_t* prow, int q,
-                                           typename ThetaTraits<PREC>::BFrag* bx) {
+__device__ __forceinline__ SpinBits load_bfrag(const int8_t* srow, const uint8_t* prow, int q,
+                                               typename ThetaTraits<PREC>::BFrag* bx) {
   constexpr int NK = nk_of<N, PREC>();
+  const SpinBits m = spin_bits<N>(srow);
   if constexpr (PREC == NQS_BF16X2) {
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
-      bf16x8 v;
+      uint32_t w[4];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int kap = 32 * kk + 8 * q + e;
-        float x = 0.f;
-        if (kap < 2 * N) x = 0.5f * (float)srow[prow[kap < N ? kap : kap - N]];
-        v[e] = (__bf16)x;
+      for (int e2 = 0; e2 < 4; ++e2) {
+        uint32_t half[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int kap = 32 * kk + 8 * q + 2 * e2 + h;
+          half[h] = kap < 2 * N ? x_bits<N>(m, prow[kap < N ? kap : kap - N]) : 0u;
+        }
+        w[e2] = (half[0] >> 16) | (half[1] & 0xffff0000u);   // two BF16, low element first
       }
-      bx[kk] = v;
+      bx[kk] = __builtin_bit_cast(bf16x8, w);
     }
   } else {
     using R = typename ThetaTraits<PREC>::R;
 #pragma unroll
-    for (int kk = 0; kk < NK; ++kk) bx[kk] = R(0.5) * (R)srow[prow[4 * kk + q]];
+    for (int kk = 0; kk < NK; ++kk) bx[kk] = (R)__uint_as_float(x_bits<N>(m, prow[4 * kk + q]));
   }
+  return m;
 }
 
 // One hidden unit of the epilogue.  With x = Re theta, y = Im theta = k pi + r
