@@ -97,6 +97,35 @@ __device__ __forceinline__ void swap32(int& x, int& y) {
   y = (int)r[1];
 }
 
+// Combination over the four rows (q = lane / 16) of a per-lane value, left
+// in every lane: a swap16 and a swap32 step, each pairing rows.
+template <typename V, typename Op>
+__device__ __forceinline__ V allreduce_rows(V v, Op op) {
+  V y = v;
+  swap16(v, y);
+  v = op(v, y);
+  y = v;
+  swap32(v, y);
+  return op(v, y);
+}
+// The same for a complex product (re, im).
+template <typename R>
+__device__ __forceinline__ void allprod_rows(R& pr, R& pi) {
+  R yr = pr, yi = pi;
+  swap16(pr, yr);
+  swap16(pi, yi);
+  R nr = pr * yr - pi * yi;
+  pi = pr * yi + pi * yr;
+  pr = nr;
+  yr = pr;
+  yi = pi;
+  swap32(pr, yr);
+  swap32(pi, yi);
+  nr = pr * yr - pi * yi;
+  pi = pr * yi + pi * yr;
+  pr = nr;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -72,18 +72,11 @@ __device__ __forceinline__ void theta_block(
         xi = fmaf_t(xj, ak[2 * j + 1], xi);
       }
     }
-    int E = pe;
-#pragma unroll
-    for (int o = 16; o <= 32; o <<= 1) {
-      const R orr = __shfl_xor(pr, o, 64), oi = __shfl_xor(pi, o, 64);
-      const R nr = pr * orr - pi * oi;
-      pi = pr * oi + pi * orr;
-      pr = nr;
-      E += __shfl_xor(E, o, 64);
-      sax += __shfl_xor(sax, o, 64);
-      xr += __shfl_xor(xr, o, 64);
-      xi += __shfl_xor(xi, o, 64);
-    }
+    allprod_rows(pr, pi);
+    const int E = allreduce_rows(pe, [](int u, int v) { return u + v; });
+    sax = allreduce_rows(sax, [](double u, double v) { return u + v; });
+    xr = allreduce_rows(xr, [](R u, R v) { return u + v; });
+    xi = allreduce_rows(xi, [](R u, R v) { return u + v; });
     Er[k] = (double)xr + sax + (double)E * 0.69314718055994530942;
     Pr[k] = pr;
     Pi[k] = pi;

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
       const int g = (active ? blk : 0) * 16 + c;
       const uint8_t* prow = perm + (size_t)g * N;
       typename T::BFrag bx[NK];
-      load_bfrag<N, PREC>(srow, prow, q, bx);
+      load_bfrag_gather<N, PREC>(srow, prow, q, bx);
       const float ch_g = (float)chi[g];
       double m_item = -INFINITY, Qr = 0.0, Qi = 0.0, denr = 0.0, deni = 0.0;
 

@@ -146,6 +146,32 @@ __device__ __forceinline__ SpinBits load_bfrag(const int8_t* srow, const uint8_t
   return m;
 }
 
+// The same fragments gathered byte by byte from the spin row (measured faster
+// in the wide E_loc kernel, whose fragments live across long chunk loops).
+template <int N, int PREC>
+__device__ __forceinline__ void load_bfrag_gather(const int8_t* srow, const uint8_t* prow, int q,
+                                                  typename ThetaTraits<PREC>::BFrag* bx) {
+  constexpr int NK = nk_of<N, PREC>();
+  if constexpr (PREC == NQS_BF16X2) {
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      bf16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int kap = 32 * kk + 8 * q + e;
+        float x = 0.f;
+        if (kap < 2 * N) x = 0.5f * (float)srow[prow[kap < N ? kap : kap - N]];
+        v[e] = (__bf16)x;
+      }
+      bx[kk] = v;
+    }
+  } else {
+    using R = typename ThetaTraits<PREC>::R;
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) bx[kk] = R(0.5) * (R)srow[prow[4 * kk + q]];
+  }
+}
+
 // One hidden unit of the epilogue.  With x = Re theta, y = Im theta = k pi + r
 // and e = exp(-2|x|):
 //   2 cosh(theta) = e^{|x|} (-1)^k c,  c = (1+e) cos r + i sgn(x) (1-e) sin r,
@@ -166,7 +192,7 @@ __device__ __forceinline__ R logcosh_step(R x, R y, R& pr, R& pi, uint32_t& par,
   pi = fmaf_t(pr, ci, pi * cr);
   pr = nr;
   if constexpr (WANT_T) {
-    const R d = fmaf_t(e + e, fmaf_t(cs, cs, -(sn * sn)), fmaf_t(e, e, R(1)));
+    const R d = fmaf_t(e + e, fmaf_t(cs, cs, -(sn * sn)), fmaf_t(e, e, R(1)));   // |c|^2
     const R inv = rcp_t(d);
     const R tu = fmaf_t(-e, e, R(1)) * inv;
     tr = x < R(0) ? -tu : tu;
