@@ -60,8 +60,8 @@ def n_antiparallel(spins, bonds):
 
 
 COUNTER_JSON = os.path.join(ROOT, "profiles", "eloc_fused_6x6_m72_hbm_counters.json")
-COUNTER_SOURCES = ["k_eloc_fused.hip", "theta_common.h", "device_common.h", "nqs_internal.h",
-                   "lds_layout.cpp"]
+COUNTER_SOURCES = ["k_eloc_fused.hip", "fused_theta.h", "theta_common.h", "device_common.h",
+                   "nqs_internal.h", "lds_layout.cpp"]
 
 
 def source_hash(files):
@@ -381,6 +381,8 @@ def main():
     ap.add_argument("--workload", default="6x6_fp32_eloc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true")
+    ap.add_argument("--legs", default="grad,logpsi,lanczos,precision,sr",
+                    help="comma-separated subset of the extra legs to run")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--write-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -408,7 +410,8 @@ def main():
     # they follow the distribution the sampler produces)
     cpu, refs = None, None
     if not args.no_cpu_baseline:
-        extra = () if args.no_legs else (precision_leg_refs("8x8_k4_m256"),)
+        want_prec = not args.no_legs and "precision" in args.legs.split(",")
+        extra = (precision_leg_refs("8x8_k4_m256"),) if want_prec else ()
         cpu, refs = cpu_baseline(args.workload, params, spins_np, extra=extra)
         log(f"cpu baseline done: {cpu['value']:.3g} {cpu['unit']} on {cpu['cores']} cores")
     spins_random = spins_np
@@ -464,7 +467,7 @@ def main():
     flops_per_launch = FLOPS_PER_FACTOR * factors_per_step / launches_per_step
     avg_ms = ms_bonds / n_bonds
     achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
-    roofline = {"kernel": "eloc_bonds", "bound": "alu", "achieved": achieved,
+    roofline = {"kernel": "eloc_fused_kernel", "bound": "alu", "achieved": achieved,
                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                 "traffic": counted_traffic() if args.workload == "6x6_fp32_eloc" else None,
@@ -502,16 +505,21 @@ def main():
         "errors": errs,
     }
     legs = {"sample": sample_leg}
-    if not args.no_legs:
+    which = set() if args.no_legs else set(args.legs.split(","))
+    if "grad" in which:
         legs["grad"] = leg_grad(m, sp, S, w.G, w.n_rbm)
         log(f"grad leg: {legs['grad']['ms']:.2f} ms")
+    if "logpsi" in which:
         legs["logpsi"] = leg_logpsi(m, sp, S, w)
         log(f"logpsi leg: {legs['logpsi']['ms']:.2f} ms")
+    if "lanczos" in which:
         legs["lanczos_two_hop"] = leg_lanczos()
         log(f"lanczos leg: {legs['lanczos_two_hop']['ms']:.2f} ms")
+    if "precision" in which:
         legs["bf16x2_vs_fp32_8x8"] = leg_precision(
             "8x8_k4_m256", None if refs is None or not refs["extra"] else refs["extra"][0])
         log("precision leg done")
+    if "sr" in which:
         legs["sr_10x10"] = leg_sr()
         log(f"sr leg: {legs['sr_10x10']['ms_sr']:.1f} ms")
     result["legs"] = legs
