@@ -25,6 +25,7 @@ from .grad import logderiv, logderiv_fd
 from .sr import sr_param_space, sr_sample_space
 from .philox import philox4x64_10, uniform53
 from .sampler import exchange_metropolis
+from .observables import momenta, correlations, structure_factor
 
 __all__ = [
     "Lattice", "C4V_CHARACTERS", "POINT_OPS", "POINT_CLASS", "Model",
@@ -34,4 +35,5 @@ __all__ = [
     "moments", "lanczos_p1", "lanczos_p1_explicit",
     "logderiv", "logderiv_fd", "sr_param_space", "sr_sample_space",
     "philox4x64_10", "uniform53", "exchange_metropolis",
+    "momenta", "correlations", "structure_factor",
 ]
