@@ -62,7 +62,7 @@ typedef enum {
 
 typedef enum {
     NQS_OP_LOGPSI = 0, NQS_OP_ELOC = 1, NQS_OP_MOMENTS = 2,
-    NQS_OP_GRAD = 3, NQS_OP_SR = 4, NQS_OP_SAMPLE = 5
+    NQS_OP_GRAD = 3, NQS_OP_SR = 4, NQS_OP_SAMPLE = 5, NQS_OP_SQ = 6
 } nqs_op;
 
 typedef struct {
@@ -161,6 +161,22 @@ nqs_status nqs_sr_solve(nqs_ctx* ctx, const void* O, const double* eloc, int64_t
 nqs_status nqs_enumerate_sz0(nqs_ctx* ctx, int8_t* spins_out, int64_t cap, int64_t* count,
                              hipStream_t stream);
 
+/* Spin structure factor (Sec. 4, the equation defining S(q), with
+ * sigma^z = +-1/2): for every momentum q = 2 pi (kx, ky) / L of the lattice,
+ * out[kx + L ky] = sum_s w_s |sum_i sigma_i e^{i q.r_i}|^2 / (N^2 sum_s w_s),
+ * the weighted mean over the configurations of the per-configuration
+ * (1/N^2) sum_{i,j} sigma_i sigma_j e^{i q.(r_i - r_j)}.  The paper's tables
+ * show N S(q).  spins: device int8 [S][N]; weights: device FP64 [S],
+ * non-negative (e.g. |psi|^2 for an exact sum over the Sz = 0 sector), or
+ * NULL for uniform weights (Monte-Carlo samples); out: device FP64 [N].
+ * Workspace: nqs_workspace_bytes(NQS_OP_SQ, S) bytes (per-block partial sums).
+ * NQS_ERR_ARG if S < 1 or a pointer is NULL; a zero weight sum gives NaN.
+ * Asynchronous on the stream; the result does not depend on the grid (the
+ * partial sums are added in a fixed order). */
+nqs_status nqs_structure_factor(nqs_ctx* ctx, const int8_t* spins, int64_t S,
+                                const double* weights, double* out, void* ws, size_t ws_bytes,
+                                hipStream_t stream);
+
 /* Pack initial configurations into chain states: chain_state [n][4] uint64
  * = {spin bits 0..63, spin bits 64..127, proposal counter = 0, chain id}
  * with chain ids first_chain_id + c.  spins: [n][N] int8 (Sz = 0). */
@@ -200,7 +216,8 @@ nqs_status nqs_set_factor_form(nqs_ctx* ctx, int direct_only);
  * `kernel` (0 theta, 1 lse, 2 eloc_bonds, 3 eloc_finish, 4 twohop,
  * 5 twohop_finish, 6 moments, 7 grad, 8 sample, 9 sr (whole nqs_sr_solve),
  * 10 gram (the S x S Gram matrix of nqs_sr_solve), 11 cholesky (its blocked
- * factorisation and the two triangular solves)), the summed duration
+ * factorisation and the two triangular solves), 12 sq (nqs_structure_factor)),
+ * the summed duration
  * in ms and the launch count since the last reset; reset = 1 clears them. */
 nqs_status nqs_profile_enable(nqs_ctx* ctx, int on);
 nqs_status nqs_profile_read(nqs_ctx* ctx, int kernel, double* ms_out, int64_t* launches_out,

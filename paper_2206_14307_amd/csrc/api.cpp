@@ -200,6 +200,7 @@ size_t nqs_workspace_bytes(const nqs_ctx* c, int op, int64_t S) {
   if (!c || S < 0) return 0;
   if (op == NQS_OP_SR) return sr_workspace_bytes(c, S);
   if (op == NQS_OP_SAMPLE) return sample_workspace_bytes(c, S);
+  if (op == NQS_OP_SQ) return sq_workspace_bytes(c, S);
   return plan(c, op, S, nullptr).bytes;
 }
 
@@ -333,6 +334,19 @@ nqs_status nqs_set_params(nqs_ctx* c, const double* params, hipStream_t st) {
       hipSuccess)
     return hip_fail(c, e, "memcpy params");
   if ((e = prep_tables(c, st)) != hipSuccess) return hip_fail(c, e, "prep");
+  return NQS_OK;
+}
+
+nqs_status nqs_structure_factor(nqs_ctx* c, const int8_t* spins, int64_t S, const double* weights,
+                                double* out, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (!c) return NQS_ERR_ARG;
+  if (S < 1) return fail(c, NQS_ERR_ARG, "structure factor needs S >= 1");
+  if (!spins || !out) return fail(c, NQS_ERR_ARG, "spins or out is NULL");
+  const size_t need = sq_workspace_bytes(c, S);
+  if (!ws || ws_bytes < need)
+    return fail(c, NQS_ERR_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
+  const hipError_t e = NQS_RUN(c, K_SQ, st, launch_sq(c, spins, S, weights, out, ws, st));
+  if (e != hipSuccess) return hip_fail(c, e, "structure factor launch");
   return NQS_OK;
 }
 

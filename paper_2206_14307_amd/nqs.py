@@ -19,15 +19,16 @@ NQS_OK, NQS_ERR_ARG, NQS_ERR_DEVICE, NQS_ERR_OOM, NQS_ERR_NONFINITE, NQS_WARN_DE
     NQS_ERR_NOT_PD = range(7)
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 IRREP = {"A1": 0, "A2": 1, "B1": 2, "B2": 3}
-OP = {"logpsi": 0, "eloc": 1, "moments": 2, "grad": 3, "sr": 4, "sample": 5}
+OP = {"logpsi": 0, "eloc": 1, "moments": 2, "grad": 3, "sr": 4, "sample": 5, "sq": 6}
 
 EXPORTS = ["nqs_create", "nqs_destroy", "nqs_num_params", "nqs_workspace_bytes", "nqs_set_params",
            "nqs_logpsi", "nqs_eloc", "nqs_lanczos_moments", "nqs_grad", "nqs_sr_solve",
            "nqs_chain_init", "nqs_sample", "nqs_enumerate_sz0", "nqs_set_factor_form",
+           "nqs_structure_factor",
            "nqs_profile_enable", "nqs_profile_read", "nqs_status_str", "nqs_last_error"]
 KERNELS = {"theta": 0, "lse": 1, "eloc_bonds": 2, "eloc_finish": 3, "twohop": 4,
            "twohop_finish": 5, "moments": 6, "grad": 7, "sample": 8, "sr": 9, "gram": 10,
-           "cholesky": 11}
+           "cholesky": 11, "sq": 12}
 
 
 class ModelDesc(C.Structure):
@@ -76,6 +77,7 @@ def load_library(path: str = LIB_PATH):
         "nqs_sample": ([vp, i64, i64, i32, i32, u64, vp, vp, vp, vp, vp, C.c_size_t, vp], C.c_int),
         "nqs_enumerate_sz0": ([vp, vp, i64, C.POINTER(i64), vp], C.c_int),
         "nqs_set_factor_form": ([vp, C.c_int], C.c_int),
+        "nqs_structure_factor": ([vp, vp, i64, vp, vp, vp, C.c_size_t, vp], C.c_int),
         "nqs_profile_enable": ([vp, C.c_int], C.c_int),
         "nqs_profile_read": ([vp, C.c_int, C.POINTER(dbl), C.POINTER(i64), C.c_int], C.c_int),
         "nqs_status_str": ([C.c_int], C.c_char_p),
@@ -187,6 +189,24 @@ class NQS:
         n = C.c_int64(0)
         self._check(self.lib.nqs_enumerate_sz0(self._ctx, _ptr(out), D, C.byref(n), _stream()),
                     "nqs_enumerate_sz0")
+        return out
+
+    def structure_factor(self, spins, weights=None):
+        """S(q) for every momentum q = 2 pi (kx, ky) / L (index kx + L ky), float64 [N]:
+        the mean over the configurations, weighted by `weights` (FP64 [S], e.g.
+        |psi|^2) when given.  The paper's tables show N S(q)."""
+        sp = self._spins(spins)
+        S = sp.shape[0]
+        w = None
+        if weights is not None:
+            w = torch.as_tensor(weights, dtype=torch.float64).to(self.device).contiguous()
+            if w.shape != (S,):
+                raise ValueError(f"weights must be float64 [{S}]")
+        out = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        ws = self.workspace("sq", S)
+        self._check(self.lib.nqs_structure_factor(self._ctx, _ptr(sp), S, _ptr(w), _ptr(out),
+                                                  _ptr(ws), ws.numel(), _stream()),
+                    "nqs_structure_factor")
         return out
 
     def logpsi(self, spins):
