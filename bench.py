@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6          # MI355X published FP64 vector (and MFMA) peak
 FLOPS_PER_FACTOR = 13             # P <- P (1 + t T): complex mul, +1, complex mul
 
 
@@ -266,6 +267,29 @@ def leg_logpsi(m, sp, S, w, steps=3):
                          "flops": flops}}
 
 
+def leg_sq(m, sp, S, w, steps=5):
+    """nqs_structure_factor over the benchmark's configurations (uniform
+    weights): per configuration and momentum q, N real-times-complex FMAs
+    (4 FP64 flops each) and |F(q)|^2; timed on the library's own events."""
+    m.structure_factor(sp)
+    import torch
+    torch.cuda.synchronize()
+    m.profile(True)
+    m.profile_read("sq", reset=True)
+    for _ in range(steps):
+        m.structure_factor(sp)
+    ms, n = m.profile_read("sq", reset=True)
+    m.profile(False)
+    ms /= max(n, 1)
+    flops = (4.0 * w.N + 3.0) * w.N * S
+    nbytes = S * (w.N + 8)
+    return {"S": S, "ms": ms, "configs_per_s": S / (ms / 1e3),
+            "roofline": {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12,
+                         "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                         "frac": flops / (ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, "flops": flops,
+                         "hbm_GBps": nbytes / (ms / 1e3) / 1e9}}
+
+
 def leg_grad(m, sp, S, G, K, steps=3):
     import torch
     O = torch.empty((S, m.P), dtype=m.o_dtype, device="cuda")
@@ -381,7 +405,7 @@ def main():
     ap.add_argument("--workload", default="6x6_fp32_eloc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true")
-    ap.add_argument("--legs", default="grad,logpsi,lanczos,precision,sr",
+    ap.add_argument("--legs", default="grad,logpsi,sq,lanczos,precision,sr",
                     help="comma-separated subset of the extra legs to run")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (HBM counter calibration)")
@@ -512,6 +536,9 @@ def main():
     if "logpsi" in which:
         legs["logpsi"] = leg_logpsi(m, sp, S, w)
         log(f"logpsi leg: {legs['logpsi']['ms']:.2f} ms")
+    if "sq" in which:
+        legs["structure_factor"] = leg_sq(m, sp, S, w)
+        log(f"structure factor leg: {legs['structure_factor']['ms']:.3f} ms")
     if "lanczos" in which:
         legs["lanczos_two_hop"] = leg_lanczos()
         log(f"lanczos leg: {legs['lanczos_two_hop']['ms']:.2f} ms")

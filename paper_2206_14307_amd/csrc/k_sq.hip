@@ -8,10 +8,12 @@
 //
 // One wavefront per configuration at a time, one lane per momentum (two for
 // N > 64).  The spin row becomes a wave-uniform mask of up spins (one vote),
-// so s_i is a scalar for every site; the phases e^{2 pi i m / L} come from a
-// small LDS table and each lane steps its phase index m = kx x + ky y (mod L)
-// along the row.  Blocks write partial sums (per momentum, and the weight
-// sum) to the workspace; a finish kernel adds them in a fixed order.
+// so s_i is a scalar for every site.  The transform is separable,
+// F(q) = sum_y e^{i ky' y} sum_x s_{x,y} e^{i kx' x} (kx' = 2 pi kx / L), so
+// each lane keeps its two rows of L phases in registers: two FMAs per site
+// and one complex product per lattice row, independent across rows.  Blocks
+// write partial sums (per momentum, and the weight sum) to the workspace; a
+// finish kernel adds them in a fixed order.
 #include <algorithm>
 
 #include "device_common.h"
@@ -29,22 +31,18 @@ __global__ __launch_bounds__(64 * kSqWaves) void sq_kernel(const int8_t* __restr
                                                            const double* __restrict__ weights,
                                                            double* __restrict__ part) {
   constexpr int N = L * L, NQL = (N + 63) / 64;
-  __shared__ double2 tw[L];
   __shared__ double red[kSqWaves][N + 1];
-  if (threadIdx.x < L) {
-    double sn, cs;
-    sincospi(2.0 * (double)threadIdx.x / L, &sn, &cs);
-    tw[threadIdx.x] = make_double2(cs, sn);
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int kx[NQL], ky[NQL];
-  double acc[NQL];
+  double cxr[NQL][L], cxi[NQL][L], cyr[NQL][L], cyi[NQL][L], acc[NQL];
 #pragma unroll
   for (int u = 0; u < NQL; ++u) {
     const int q = (lane + 64 * u) % N;   // lanes past N repeat a momentum, unused
-    kx[u] = q % L;
-    ky[u] = q / L;
+    const int kx = q % L, ky = q / L;
+#pragma unroll
+    for (int v = 0; v < L; ++v) {
+      sincospi(2.0 * (double)((kx * v) % L) / L, &cxi[u][v], &cxr[u][v]);
+      sincospi(2.0 * (double)((ky * v) % L) / L, &cyi[u][v], &cyr[u][v]);
+    }
     acc[u] = 0.0;
   }
   double wsum = 0.0;
@@ -60,18 +58,17 @@ __global__ __launch_bounds__(64 * kSqWaves) void sq_kernel(const int8_t* __restr
       double fr = 0.0, fi = 0.0;
 #pragma unroll
       for (int y = 0; y < L; ++y) {
-        int m = (ky[u] * y) % L;
+        double rr = 0.0, ri = 0.0;
 #pragma unroll
         for (int x = 0; x < L; ++x) {
           const int i = x + L * y;
           const bool up = i < 64 ? ((up0 >> i) & 1ull) : ((up1 >> (i - 64)) & 1ull);
           const double sg = up ? 0.5 : -0.5;
-          const double2 t = tw[m];
-          fr = fma(sg, t.x, fr);
-          fi = fma(sg, t.y, fi);
-          m += kx[u];
-          if (m >= L) m -= L;
+          rr = fma(sg, cxr[u][x], rr);
+          ri = fma(sg, cxi[u][x], ri);
         }
+        fr = fma(rr, cyr[u][y], fma(-ri, cyi[u][y], fr));
+        fi = fma(rr, cyi[u][y], fma(ri, cyr[u][y], fi));
       }
       acc[u] = fma(ws, fma(fr, fr, fi * fi), acc[u]);
     }
@@ -90,17 +87,30 @@ __global__ __launch_bounds__(64 * kSqWaves) void sq_kernel(const int8_t* __restr
   }
 }
 
-// out[q] = sum_b part[b][q] / (N^2 sum_b part[b][N]), blocks added in order.
-__global__ __launch_bounds__(128) void sq_finish_kernel(const double* __restrict__ part, int nblk,
+// out[q] = sum_b part[b][q] / (N^2 sum_b part[b][N]): one block per momentum;
+// thread t adds the partials b = t, t + 256, ... and a fixed tree joins the
+// threads, so the result does not depend on timing.  Every block forms the
+// weight sum itself.
+__global__ __launch_bounds__(256) void sq_finish_kernel(const double* __restrict__ part, int nblk,
                                                         int N, double* __restrict__ out) {
-  __shared__ double wsum;
-  const int q = threadIdx.x;
-  double v = 0.0;
-  if (q <= N)
-    for (int b = 0; b < nblk; ++b) v += part[(size_t)b * (N + 1) + q];
-  if (q == N) wsum = v;
+  __shared__ double rv[256], rw[256];
+  const int q = blockIdx.x, t = threadIdx.x;
+  double v = 0.0, w = 0.0;
+  for (int b = t; b < nblk; b += 256) {
+    v += part[(size_t)b * (N + 1) + q];
+    w += part[(size_t)b * (N + 1) + N];
+  }
+  rv[t] = v;
+  rw[t] = w;
   __syncthreads();
-  if (q < N) out[q] = v / (wsum * (double)N * (double)N);
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      rv[t] += rv[t + h];
+      rw[t] += rw[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) out[q] = rv[0] / (rw[0] * (double)N * (double)N);
 }
 
 int sq_blocks(const nqs_ctx* c, int64_t S) {
@@ -115,7 +125,7 @@ hipError_t run_sq(const nqs_ctx* c, const int8_t* spins, int64_t S, const double
   sq_kernel<L><<<nblk, 64 * kSqWaves, 0, st>>>(spins, S, weights, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  sq_finish_kernel<<<1, 128, 0, st>>>(part, nblk, L * L, out);
+  sq_finish_kernel<<<L * L, 256, 0, st>>>(part, nblk, L * L, out);
   return hipGetLastError();
 }
 
