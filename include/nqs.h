@@ -62,7 +62,7 @@ typedef enum {
 
 typedef enum {
     NQS_OP_LOGPSI = 0, NQS_OP_ELOC = 1, NQS_OP_MOMENTS = 2,
-    NQS_OP_GRAD = 3, NQS_OP_SR = 4, NQS_OP_SAMPLE = 5, NQS_OP_SQ = 6
+    NQS_OP_GRAD = 3, NQS_OP_SR = 4, NQS_OP_SAMPLE = 5, NQS_OP_SQ = 6, NQS_OP_VMC = 7
 } nqs_op;
 
 typedef struct {
@@ -87,6 +87,15 @@ typedef struct {
     double h1, h1_im, h2, h2_alt, h3, c2, c3, v, r, alpha, e_p1, h1_err;
     int32_t degenerate;
 } nqs_moments;
+
+/* Statistics of one training step (nqs_vmc_step), all FP64. */
+typedef struct {
+    int64_t n;                  /* configurations */
+    double energy, energy_im;   /* <E_loc>, for the parameters before the update */
+    double variance;            /* <|E_loc - <E_loc>|^2> */
+    double error;               /* sqrt(variance / n) (no autocorrelation correction) */
+    double dtheta_norm;         /* ||dtheta||_2 of the applied update */
+} nqs_vmc_stats;
 
 typedef struct nqs_ctx nqs_ctx;
 
@@ -176,6 +185,24 @@ nqs_status nqs_enumerate_sz0(nqs_ctx* ctx, int8_t* spins_out, int64_t cap, int64
 nqs_status nqs_structure_factor(nqs_ctx* ctx, const int8_t* spins, int64_t S,
                                 const double* weights, double* out, void* ws, size_t ws_bytes,
                                 hipStream_t stream);
+
+/* Copy the context's current parameters (P complex values, double re, im, in
+ * the nqs_set_params layout) to params_out_dev (device memory).  Asynchronous. */
+nqs_status nqs_get_params(nqs_ctx* ctx, double* params_out_dev, hipStream_t stream);
+
+/* One stochastic-reconfiguration training step (Sec. 3.2: Eq. (12) and the
+ * update theta <- theta + dtheta after it) on S configurations, e.g. from
+ * nqs_sample: E_loc (nqs_eloc), their FP64 statistics, O_k (nqs_grad),
+ * dtheta = nqs_sr_solve(lambda, dtau); the context's parameters become
+ * theta + dtheta (the imaginary part of dtheta is dropped when
+ * real_params = 1, for real RBMs) and the tables are rebuilt.  *out
+ * describes the parameters before the update.  Workspace:
+ * nqs_workspace_bytes(NQS_OP_VMC, S).  Synchronises the stream.  Errors are
+ * those of the three calls; NQS_ERR_NONFINITE (parameters unchanged) if
+ * theta + dtheta is not finite. */
+nqs_status nqs_vmc_step(nqs_ctx* ctx, const int8_t* spins, int64_t S, double lambda, double dtau,
+                        int real_params, nqs_vmc_stats* out, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
 
 /* Pack initial configurations into chain states: chain_state [n][4] uint64
  * = {spin bits 0..63, spin bits 64..127, proposal counter = 0, chain id}

@@ -196,11 +196,39 @@ const char* nqs_last_error(const nqs_ctx* c) { return c ? c->last_error.c_str() 
 
 int64_t nqs_num_params(const nqs_ctx* c) { return c ? c->P : -1; }
 
+namespace {
+// nqs_vmc_step workspace: E_loc [S], O [S][P], dtheta [P], theta + dtheta [P],
+// statistics, then one region shared by the eloc, grad and sr_solve calls.
+struct VmcCarve {
+  size_t eloc, O, dth, next, stats, sub, bytes;
+};
+VmcCarve vmc_carve(const nqs_ctx* c, int64_t S) {
+  VmcCarve v;
+  const size_t osz = c->prec == NQS_FP64 ? 16 : 8;
+  size_t off = 0;
+  v.eloc = off; off += align_up((size_t)S * 16);
+  v.O = off; off += align_up((size_t)S * c->P * osz);
+  v.dth = off; off += align_up((size_t)c->P * 16);
+  v.next = off; off += align_up((size_t)c->P * 16);
+  v.stats = off; off += align_up(8 * 8);
+  v.sub = off;
+  size_t sub = plan(c, NQS_OP_ELOC, S, nullptr).bytes;
+  sub = std::max(sub, plan(c, NQS_OP_GRAD, S, nullptr).bytes);
+  sub = std::max(sub, sr_workspace_bytes(c, S));
+  v.bytes = off + align_up(std::max<size_t>(sub, 1));
+  return v;
+}
+size_t vmc_workspace_bytes(const nqs_ctx* c, int64_t S) {
+  return vmc_carve(c, std::max<int64_t>(S, 1)).bytes;
+}
+}  // namespace
+
 size_t nqs_workspace_bytes(const nqs_ctx* c, int op, int64_t S) {
   if (!c || S < 0) return 0;
   if (op == NQS_OP_SR) return sr_workspace_bytes(c, S);
   if (op == NQS_OP_SAMPLE) return sample_workspace_bytes(c, S);
   if (op == NQS_OP_SQ) return sq_workspace_bytes(c, S);
+  if (op == NQS_OP_VMC) return vmc_workspace_bytes(c, S);
   return plan(c, op, S, nullptr).bytes;
 }
 
@@ -331,6 +359,58 @@ nqs_status nqs_set_params(nqs_ctx* c, const double* params, hipStream_t st) {
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "sync");
   if (flag != 0.0) return fail(c, NQS_ERR_NONFINITE, "parameters contain NaN or Inf");
   if ((e = hipMemcpyAsync(c->par.params, params, (size_t)c->P * 16, hipMemcpyDeviceToDevice, st)) !=
+      hipSuccess)
+    return hip_fail(c, e, "memcpy params");
+  if ((e = prep_tables(c, st)) != hipSuccess) return hip_fail(c, e, "prep");
+  return NQS_OK;
+}
+
+nqs_status nqs_get_params(nqs_ctx* c, double* params_out, hipStream_t st) {
+  if (!c) return NQS_ERR_ARG;
+  if (!params_out) return fail(c, NQS_ERR_ARG, "params_out is NULL");
+  const hipError_t e = hipMemcpyAsync(params_out, c->par.params, (size_t)c->P * 16,
+                                      hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(c, e, "memcpy params");
+  return NQS_OK;
+}
+
+nqs_status nqs_vmc_step(nqs_ctx* c, const int8_t* spins, int64_t S, double lambda, double dtau,
+                        int real_params, nqs_vmc_stats* out, void* ws, size_t ws_bytes,
+                        hipStream_t st) {
+  if (!c) return NQS_ERR_ARG;
+  if (S < 1 || !spins || !out) return fail(c, NQS_ERR_ARG, "vmc_step: needs S >= 1, spins, out");
+  const VmcCarve v = vmc_carve(c, S);
+  if (!ws || ws_bytes < v.bytes)
+    return fail(c, NQS_ERR_ARG, "vmc_step: workspace too small: need " + std::to_string(v.bytes));
+  char* base = (char*)ws;
+  double* eloc = (double*)(base + v.eloc);
+  void* O = base + v.O;
+  double* dth = (double*)(base + v.dth);
+  double* next = (double*)(base + v.next);
+  double* stats = (double*)(base + v.stats);
+  void* sub = base + v.sub;
+  const size_t sub_bytes = v.bytes - v.sub;
+  nqs_status s = nqs_eloc(c, spins, S, nullptr, eloc, sub, sub_bytes, st);
+  if (s != NQS_OK) return s;
+  hipError_t e = launch_energy_stats(eloc, S, stats, st);
+  if (e != hipSuccess) return hip_fail(c, e, "energy statistics");
+  if ((s = nqs_grad(c, spins, S, O, nullptr, sub, sub_bytes, st)) != NQS_OK) return s;
+  if ((s = nqs_sr_solve(c, O, eloc, S, lambda, dtau, dth, sub, sub_bytes, st)) != NQS_OK) return s;
+  if ((e = launch_params_step(c->par.params, dth, c->P, real_params ? 0 : 1, next, stats, st)) !=
+      hipSuccess)
+    return hip_fail(c, e, "parameter step");
+  double h[5];
+  if ((e = hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return hip_fail(c, e, "memcpy stats");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "sync");
+  out->n = S;
+  out->energy = h[0];
+  out->energy_im = h[1];
+  out->variance = h[2];
+  out->error = std::sqrt(h[2] / (double)S);
+  out->dtheta_norm = h[3];
+  if (h[4] != 0.0) return fail(c, NQS_ERR_NONFINITE, "vmc_step: theta + dtheta is not finite");
+  if ((e = hipMemcpyAsync(c->par.params, next, (size_t)c->P * 16, hipMemcpyDeviceToDevice, st)) !=
       hipSuccess)
     return hip_fail(c, e, "memcpy params");
   if ((e = prep_tables(c, st)) != hipSuccess) return hip_fail(c, e, "prep");

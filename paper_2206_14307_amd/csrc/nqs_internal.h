@@ -172,6 +172,9 @@ hipError_t launch_moments(const double* e1e2, const double* logpsi, int64_t S, i
 size_t sample_workspace_bytes(const nqs_ctx* c, int64_t n_chains);
 size_t sr_workspace_bytes(const nqs_ctx* c, int64_t S);
 size_t sq_workspace_bytes(const nqs_ctx* c, int64_t S);
+hipError_t launch_energy_stats(const double* eloc, int64_t S, double* stats, hipStream_t st);
+hipError_t launch_params_step(const double* params, const double* dtheta, int64_t P, int is_complex,
+                              double* next, double* stats, hipStream_t st);
 hipError_t launch_sq(const nqs_ctx* c, const int8_t* spins, int64_t S, const double* weights,
                      double* out, void* ws, hipStream_t st);
 hipError_t launch_grad(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,

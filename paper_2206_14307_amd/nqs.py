@@ -19,12 +19,12 @@ NQS_OK, NQS_ERR_ARG, NQS_ERR_DEVICE, NQS_ERR_OOM, NQS_ERR_NONFINITE, NQS_WARN_DE
     NQS_ERR_NOT_PD = range(7)
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 IRREP = {"A1": 0, "A2": 1, "B1": 2, "B2": 3}
-OP = {"logpsi": 0, "eloc": 1, "moments": 2, "grad": 3, "sr": 4, "sample": 5, "sq": 6}
+OP = {"logpsi": 0, "eloc": 1, "moments": 2, "grad": 3, "sr": 4, "sample": 5, "sq": 6, "vmc": 7}
 
 EXPORTS = ["nqs_create", "nqs_destroy", "nqs_num_params", "nqs_workspace_bytes", "nqs_set_params",
            "nqs_logpsi", "nqs_eloc", "nqs_lanczos_moments", "nqs_grad", "nqs_sr_solve",
            "nqs_chain_init", "nqs_sample", "nqs_enumerate_sz0", "nqs_set_factor_form",
-           "nqs_structure_factor",
+           "nqs_structure_factor", "nqs_get_params", "nqs_vmc_step",
            "nqs_profile_enable", "nqs_profile_read", "nqs_status_str", "nqs_last_error"]
 KERNELS = {"theta": 0, "lse": 1, "eloc_bonds": 2, "eloc_finish": 3, "twohop": 4,
            "twohop_finish": 5, "moments": 6, "grad": 7, "sample": 8, "sr": 9, "gram": 10,
@@ -41,6 +41,11 @@ class Moments(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, C.c_double) for k in (
         "h1", "h1_im", "h2", "h2_alt", "h3", "c2", "c3", "v", "r", "alpha", "e_p1", "h1_err")] + [
         ("degenerate", C.c_int32)]
+
+
+class VmcStats(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(k, C.c_double) for k in (
+        "energy", "energy_im", "variance", "error", "dtheta_norm")]
 
 
 class NQSError(RuntimeError):
@@ -78,6 +83,9 @@ def load_library(path: str = LIB_PATH):
         "nqs_enumerate_sz0": ([vp, vp, i64, C.POINTER(i64), vp], C.c_int),
         "nqs_set_factor_form": ([vp, C.c_int], C.c_int),
         "nqs_structure_factor": ([vp, vp, i64, vp, vp, vp, C.c_size_t, vp], C.c_int),
+        "nqs_get_params": ([vp, vp, vp], C.c_int),
+        "nqs_vmc_step": ([vp, vp, i64, dbl, dbl, C.c_int, C.POINTER(VmcStats), vp, C.c_size_t, vp],
+                         C.c_int),
         "nqs_profile_enable": ([vp, C.c_int], C.c_int),
         "nqs_profile_read": ([vp, C.c_int, C.POINTER(dbl), C.POINTER(i64), C.c_int], C.c_int),
         "nqs_status_str": ([C.c_int], C.c_char_p),
@@ -170,7 +178,25 @@ class NQS:
             raise ValueError(f"expected {self.P} parameters, got {p.numel()}")
         self._check(self.lib.nqs_set_params(self._ctx, _ptr(torch.view_as_real(p)), _stream()),
                     "nqs_set_params")
-        self.params = p
+
+    def get_params(self):
+        """The context's current parameters, complex128 [P] (nqs_set_params layout)."""
+        out = torch.empty(self.P, dtype=torch.complex128, device=self.device)
+        self._check(self.lib.nqs_get_params(self._ctx, _ptr(torch.view_as_real(out)), _stream()),
+                    "nqs_get_params")
+        return out
+
+    def vmc_step(self, spins, lam=1e-6, dtau=0.01, real_params=False):
+        """One SR training step on the configurations (nqs_vmc_step): returns the
+        energy statistics of the parameters before the update."""
+        sp = self._spins(spins)
+        S = sp.shape[0]
+        ws = self.workspace("vmc", S)
+        st = VmcStats()
+        self._check(self.lib.nqs_vmc_step(self._ctx, _ptr(sp), S, float(lam), float(dtau),
+                                          int(bool(real_params)), C.byref(st), _ptr(ws),
+                                          ws.numel(), _stream()), "nqs_vmc_step")
+        return {k: getattr(st, k) for k, _ in VmcStats._fields_}
 
     def set_factor_form(self, direct_only):
         self._check(self.lib.nqs_set_factor_form(self._ctx, int(bool(direct_only))),
