@@ -290,6 +290,59 @@ def leg_sq(m, sp, S, w, steps=5):
                          "hbm_GBps": nbytes / (ms / 1e3) / 1e9}}
 
 
+def leg_vmc(steps=3):
+    """SR training at the paper's step size (10 000 samples per step, Sec. 3.4)
+    on the 6x6 M = 72 FP32 model: time of nqs_sample (1000 chains x 10 samples,
+    N_skip = 5/r from the previous step) and of nqs_vmc_step (E_loc, statistics,
+    O_k, the 10 000 x 10 000 sample-space SR solve, update).  Then the 4x4
+    complex M = 16 model trained for 200 steps of 2048 samples from
+    N(0, 0.01): its exact energy against exact diagonalisation of the
+    4 x 4 lattice is computed on the GPU over the whole Sz = 0 sector."""
+    import dataclasses
+    import torch
+    from paper_2206_14307_amd import NQS
+    from paper_2206_14307_amd.vmc import nskip_from_acceptance, train
+    from workloads import WORKLOADS, draw_params, random_sz0_spins_fast
+    w = WORKLOADS["6x6_fp32_eloc"]
+    m = NQS.from_workload(w)
+    m.set_params(torch.from_numpy(draw_params(w).reshape(-1)))
+    state = m.chain_init(torch.from_numpy(random_sz0_spins_fast(w.N, 1000, 77)).cuda())
+    nskip, t_s, t_v, rec = 0, [], [], None
+    for step in range(steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sp, acc, ns = m.sample(state, 10, n_skip=nskip, n_burn=20 * w.N if step == 0 else 0,
+                               seed=77)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rec = m.vmc_step(sp, lam=1e-6, dtau=0.01)
+        t2 = time.perf_counter()
+        if step > 0:                                   # the first step carries the burn-in
+            t_s.append(t1 - t0)
+            t_v.append(t2 - t1)
+        nskip = nskip_from_acceptance(float(acc.cpu().double().mean()))
+    out = {"workload": "6x6_fp32_eloc", "samples_per_step": 10000, "n_skip": nskip,
+           "ms_sample": 1e3 * sum(t_s) / len(t_s), "ms_vmc_step": 1e3 * sum(t_v) / len(t_v),
+           "energy_per_site": rec["energy"] / w.N}
+    out["ms_per_training_step"] = out["ms_sample"] + out["ms_vmc_step"]
+    w4 = dataclasses.replace(WORKLOADS["4x4_fp64_exact"], is_complex=True, J2=0.0)
+    m4 = NQS.from_workload(w4)
+    m4.set_params(torch.from_numpy(draw_params(w4).reshape(-1)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = train(m4, torch.from_numpy(random_sz0_spins_fast(w4.N, 256, 3)).cuda(), steps=200,
+                 n_per_chain=8, dtau=0.05)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    res, _ = m4.lanczos_moments(m4.enumerate_sz0(), exact=True)
+    e0 = -0.701780 * w4.N          # 4x4 Heisenberg ground state (exact diagonalisation)
+    out["train_4x4_j2_0"] = {"steps": len(hist), "seconds": t_train,
+                             "exact_energy": res["h1"], "e_p1": res["e_p1"], "e0_ed": e0,
+                             "rel_err": abs(res["h1"] - e0) / abs(e0),
+                             "rel_err_p1": abs(res["e_p1"] - e0) / abs(e0)}
+    return out
+
+
 def leg_grad(m, sp, S, G, K, steps=3):
     import torch
     O = torch.empty((S, m.P), dtype=m.o_dtype, device="cuda")
@@ -405,7 +458,7 @@ def main():
     ap.add_argument("--workload", default="6x6_fp32_eloc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true")
-    ap.add_argument("--legs", default="grad,logpsi,sq,lanczos,precision,sr",
+    ap.add_argument("--legs", default="grad,logpsi,sq,vmc,lanczos,precision,sr",
                     help="comma-separated subset of the extra legs to run")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (HBM counter calibration)")
@@ -539,6 +592,9 @@ def main():
     if "sq" in which:
         legs["structure_factor"] = leg_sq(m, sp, S, w)
         log(f"structure factor leg: {legs['structure_factor']['ms']:.3f} ms")
+    if "vmc" in which:
+        legs["vmc_training"] = leg_vmc()
+        log(f"vmc leg: {legs['vmc_training']['ms_per_training_step']:.1f} ms per 6x6 step")
     if "lanczos" in which:
         legs["lanczos_two_hop"] = leg_lanczos()
         log(f"lanczos leg: {legs['lanczos_two_hop']['ms']:.2f} ms")
