@@ -62,7 +62,8 @@ typedef enum {
 
 typedef enum {
     NQS_OP_LOGPSI = 0, NQS_OP_ELOC = 1, NQS_OP_MOMENTS = 2,
-    NQS_OP_GRAD = 3, NQS_OP_SR = 4, NQS_OP_SAMPLE = 5, NQS_OP_SQ = 6, NQS_OP_VMC = 7
+    NQS_OP_GRAD = 3, NQS_OP_SR = 4, NQS_OP_SAMPLE = 5, NQS_OP_SQ = 6, NQS_OP_VMC = 7,
+    NQS_OP_CG = 8
 } nqs_op;
 
 typedef struct {
@@ -159,6 +160,21 @@ nqs_status nqs_sr_solve(nqs_ctx* ctx, const void* O, const double* eloc, int64_t
                         double dtau, double* dtheta_out, void* ws, size_t ws_bytes,
                         hipStream_t stream);
 
+/* The same step of Eq. (12) solved in parameter space by conjugate gradients
+ * (Sec. 3.4: CG with the ridge lambda), matrix-free: A v = O_bar^H (O_bar v)
+ * + lambda v and b = -dtau O_bar^H eps with O_bar and eps as in
+ * nqs_sr_solve, centred on the fly (neither O_bar nor the P x P matrix is
+ * formed; each iteration reads O twice).  Starts from dtheta = 0 and stops
+ * when ||r|| <= tol ||b|| or after max_iter iterations.  O, eloc and
+ * dtheta_out as in nqs_sr_solve; iters_out and resid_out (host, optional)
+ * receive the iteration count and ||r|| / ||b||.  Workspace:
+ * nqs_workspace_bytes(NQS_OP_CG, S).  Synchronises the stream (once per
+ * iteration, to test the residual); NQS_ERR_NOT_PD if p^H A p <= 0. */
+nqs_status nqs_sr_solve_cg(nqs_ctx* ctx, const void* O, const double* eloc, int64_t S,
+                           double lambda, double dtau, double tol, int max_iter,
+                           double* dtheta_out, int* iters_out, double* resid_out, void* ws,
+                           size_t ws_bytes, hipStream_t stream);
+
 /* The Sz = 0 sector, i.e. all configurations with N/2 up spins (the exact
  * evaluations of Sec. 3.3 run over it on the 4x4 lattice), in colex order of
  * the up-site sets = increasing bit mask sum_{i up} 2^i: row r of
@@ -243,7 +259,8 @@ nqs_status nqs_set_factor_form(nqs_ctx* ctx, int direct_only);
  * `kernel` (0 theta, 1 lse, 2 eloc_bonds, 3 eloc_finish, 4 twohop,
  * 5 twohop_finish, 6 moments, 7 grad, 8 sample, 9 sr (whole nqs_sr_solve),
  * 10 gram (the S x S Gram matrix of nqs_sr_solve), 11 cholesky (its blocked
- * factorisation and the two triangular solves), 12 sq (nqs_structure_factor)),
+ * factorisation and the two triangular solves), 12 sq (nqs_structure_factor),
+ * 13 cg (nqs_sr_solve_cg)),
  * the summed duration
  * in ms and the launch count since the last reset; reset = 1 clears them. */
 nqs_status nqs_profile_enable(nqs_ctx* ctx, int on);

@@ -229,6 +229,7 @@ size_t nqs_workspace_bytes(const nqs_ctx* c, int op, int64_t S) {
   if (op == NQS_OP_SAMPLE) return sample_workspace_bytes(c, S);
   if (op == NQS_OP_SQ) return sq_workspace_bytes(c, S);
   if (op == NQS_OP_VMC) return vmc_workspace_bytes(c, S);
+  if (op == NQS_OP_CG) return cg_workspace_bytes(c, S);
   return plan(c, op, S, nullptr).bytes;
 }
 

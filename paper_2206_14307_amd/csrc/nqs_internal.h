@@ -77,7 +77,7 @@ struct ParamTables {
 
 namespace nqs {
 enum KernelId { K_THETA = 0, K_LSE, K_ELOC, K_ELOC_FIN, K_TWOHOP, K_TWOHOP_FIN, K_MOMENTS,
-                K_GRAD, K_SAMPLE, K_SR, K_GRAM, K_CHOL, K_SQ, K_COUNT };
+                K_GRAD, K_SAMPLE, K_SR, K_GRAM, K_CHOL, K_SQ, K_CG, K_COUNT };
 struct Profiler {
   bool on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[K_COUNT];
@@ -172,6 +172,7 @@ hipError_t launch_moments(const double* e1e2, const double* logpsi, int64_t S, i
 size_t sample_workspace_bytes(const nqs_ctx* c, int64_t n_chains);
 size_t sr_workspace_bytes(const nqs_ctx* c, int64_t S);
 size_t sq_workspace_bytes(const nqs_ctx* c, int64_t S);
+size_t cg_workspace_bytes(const nqs_ctx* c, int64_t S);
 hipError_t launch_energy_stats(const double* eloc, int64_t S, double* stats, hipStream_t st);
 hipError_t launch_params_step(const double* params, const double* dtheta, int64_t P, int is_complex,
                               double* next, double* stats, hipStream_t st);

@@ -19,16 +19,16 @@ NQS_OK, NQS_ERR_ARG, NQS_ERR_DEVICE, NQS_ERR_OOM, NQS_ERR_NONFINITE, NQS_WARN_DE
     NQS_ERR_NOT_PD = range(7)
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 IRREP = {"A1": 0, "A2": 1, "B1": 2, "B2": 3}
-OP = {"logpsi": 0, "eloc": 1, "moments": 2, "grad": 3, "sr": 4, "sample": 5, "sq": 6, "vmc": 7}
+OP = {"logpsi": 0, "eloc": 1, "moments": 2, "grad": 3, "sr": 4, "sample": 5, "sq": 6, "vmc": 7, "cg": 8}
 
 EXPORTS = ["nqs_create", "nqs_destroy", "nqs_num_params", "nqs_workspace_bytes", "nqs_set_params",
            "nqs_logpsi", "nqs_eloc", "nqs_lanczos_moments", "nqs_grad", "nqs_sr_solve",
            "nqs_chain_init", "nqs_sample", "nqs_enumerate_sz0", "nqs_set_factor_form",
-           "nqs_structure_factor", "nqs_get_params", "nqs_vmc_step",
+           "nqs_structure_factor", "nqs_get_params", "nqs_vmc_step", "nqs_sr_solve_cg",
            "nqs_profile_enable", "nqs_profile_read", "nqs_status_str", "nqs_last_error"]
 KERNELS = {"theta": 0, "lse": 1, "eloc_bonds": 2, "eloc_finish": 3, "twohop": 4,
            "twohop_finish": 5, "moments": 6, "grad": 7, "sample": 8, "sr": 9, "gram": 10,
-           "cholesky": 11, "sq": 12}
+           "cholesky": 11, "sq": 12, "cg": 13}
 
 
 class ModelDesc(C.Structure):
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH):
         "nqs_set_factor_form": ([vp, C.c_int], C.c_int),
         "nqs_structure_factor": ([vp, vp, i64, vp, vp, vp, C.c_size_t, vp], C.c_int),
         "nqs_get_params": ([vp, vp, vp], C.c_int),
+        "nqs_sr_solve_cg": ([vp, vp, vp, i64, dbl, dbl, dbl, C.c_int, vp, C.POINTER(C.c_int),
+                             C.POINTER(dbl), vp, C.c_size_t, vp], C.c_int),
         "nqs_vmc_step": ([vp, vp, i64, dbl, dbl, C.c_int, C.POINTER(VmcStats), vp, C.c_size_t, vp],
                          C.c_int),
         "nqs_profile_enable": ([vp, C.c_int], C.c_int),
@@ -288,6 +290,21 @@ class NQS:
                                           _ptr(out), _ptr(ws), ws.numel(), _stream()),
                     "nqs_sr_solve")
         return out
+
+    def sr_solve_cg(self, O, eloc, lam=1e-6, dtau=0.01, tol=1e-10, max_iter=1000):
+        """Eq. (12) by matrix-free conjugate gradients in parameter space:
+        returns (dtheta complex128 [P], iterations, relative residual)."""
+        S = O.shape[0]
+        O = O.to(self.o_dtype).contiguous()
+        el = eloc.to(torch.complex128).contiguous()
+        out = torch.empty(self.P, dtype=torch.complex128, device=self.device)
+        ws = self.workspace("cg", S)
+        it, res = C.c_int(0), C.c_double(0.0)
+        self._check(self.lib.nqs_sr_solve_cg(self._ctx, _ptr(O), _ptr(el), S, float(lam),
+                                             float(dtau), float(tol), int(max_iter), _ptr(out),
+                                             C.byref(it), C.byref(res), _ptr(ws), ws.numel(),
+                                             _stream()), "nqs_sr_solve_cg")
+        return out, it.value, res.value
 
     def chain_init(self, spins, first_chain_id=0):
         sp = self._spins(spins)

@@ -1,0 +1,95 @@
+"""Parameter-space SR by matrix-free CG (nqs_sr_solve_cg) against the
+oracle's dense solve of Eq. (12) and against the sample-space solve.
+
+O and E_loc come from the oracle (as in the sample-space tests), so the
+test isolates the CG.  The products run in FP64 on the O values as stored
+(complex64 O promoted exactly), so the solution matches the oracle's solve
+on the same values to the CG tolerance times the condition number."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import stress_params
+from workloads import WORKLOADS, draw_params, random_sz0_spins
+
+pytestmark = pytest.mark.gpu
+
+
+def make(w):
+    from paper_2206_14307_amd import NQS
+    return NQS.from_workload(w)
+
+
+@pytest.fixture(scope="module")
+def c1_inputs():
+    w = dataclasses.replace(WORKLOADS["4x4_fp64_exact"], is_complex=True)
+    p = stress_params(w, 0.1, 3)
+    om = oracle.Model.from_workload(w)
+    spins = random_sz0_spins(w.N, 400, 4)
+    return w, oracle.logderiv(om, p, spins), oracle.eloc_direct(om, p, spins)
+
+
+@pytest.mark.parametrize("S,lam", [(40, 1e-3), (400, 1e-3), (400, 1e-6)])
+def test_cg_fp64_matches_dense_solve(c1_inputs, S, lam):
+    w, O, el = c1_inputs
+    O, el = O[:S], el[:S]
+    m = make(w)
+    got, it, res = m.sr_solve_cg(torch.from_numpy(O).cuda(), torch.from_numpy(el).cuda(),
+                                 lam=lam, dtau=0.02, tol=1e-12, max_iter=5000)
+    ref = oracle.sr_param_space(O, el, lam, 0.02)
+    assert res <= 1e-12 and 0 < it < 5000
+    tol = 1e-9 if lam >= 1e-3 else 1e-6
+    assert np.linalg.norm(got.cpu().numpy() - ref) < tol * np.linalg.norm(ref)
+    # the sample-space solve of the same system (push-through identity)
+    ss = m.sr_solve(torch.from_numpy(O).cuda(), torch.from_numpy(el).cuda(), lam=lam, dtau=0.02)
+    assert np.linalg.norm(got.cpu().numpy() - ss.cpu().numpy()) < tol * np.linalg.norm(ref)
+
+
+def test_cg_fp32_o_6x6():
+    """complex64 O (FP32 models): 517 configurations (ragged against the
+    16-row and 64-row blocks), P = 2700."""
+    w = WORKLOADS["6x6_fp32_eloc"]
+    p = stress_params(dataclasses.replace(w, n_hidden=72), 0.05, 5)
+    om = oracle.Model.from_workload(w)
+    spins = random_sz0_spins(w.N, 517, 6)
+    O = oracle.logderiv(om, p, spins).astype(np.complex64)
+    el = oracle.eloc_direct(om, p, spins)
+    m = make(w)
+    got, it, res = m.sr_solve_cg(torch.from_numpy(O).cuda(), torch.from_numpy(el).cuda(),
+                                 lam=1e-3, dtau=0.01, tol=1e-12, max_iter=5000)
+    ref = oracle.sr_param_space(O.astype(np.complex128), el, 1e-3, 0.01)
+    assert res <= 1e-12
+    assert np.linalg.norm(got.cpu().numpy() - ref) < 1e-9 * np.linalg.norm(ref)
+
+
+def test_cg_10x10_against_sample_space():
+    """10x10 M = 400 (P = 40 500 parameters) at S = 1500: no oracle at this
+    size; CG and the sample-space solve (FP32 Gram) of the same system agree
+    to the sample-space solve's FP32 budget."""
+    w = WORKLOADS["10x10_m400"]
+    m = make(w)
+    m.set_params(torch.from_numpy(draw_params(w).reshape(-1)))
+    sp = torch.from_numpy(random_sz0_spins(w.N, 1500, 8)).cuda()
+    O = m.grad(sp)
+    _, el = m.eloc(sp)
+    got, it, res = m.sr_solve_cg(O, el, lam=1e-3, dtau=0.01, tol=1e-10, max_iter=2000)
+    ss = m.sr_solve(O, el, lam=1e-3, dtau=0.01)
+    assert res <= 1e-10
+    assert torch.linalg.norm(got - ss) < 1e-4 * torch.linalg.norm(ss)
+    del O
+
+
+def test_cg_edges(c1_inputs):
+    from paper_2206_14307_amd import NQSError
+    w, O, el = c1_inputs
+    m = make(w)
+    Ot, et = torch.from_numpy(O[:10]).cuda(), torch.from_numpy(el[:10]).cuda()
+    x, it, res = m.sr_solve_cg(Ot, et, lam=1e-3, dtau=0.02, tol=1e-12, max_iter=0)
+    assert it == 0 and res == pytest.approx(1.0) and torch.count_nonzero(x) == 0
+    with pytest.raises(NQSError):
+        m.sr_solve_cg(Ot, et, lam=-1.0)
+    with pytest.raises(NQSError):
+        m.sr_solve_cg(Ot, et, tol=-1.0)
