@@ -434,7 +434,21 @@ def leg_sr(name="10x10_m400", S=32768, steps=1):
         ms, n = C.c_double(0), C.c_int64(0)
         m.lib.nqs_profile_read(m._ctx, KERNELS[k], C.byref(ms), C.byref(n), 1)
         part[k] = ms.value / max(n.value, 1)
+    # the same system by matrix-free CG in parameter space (two passes over O
+    # per iteration: HBM-bound)
+    m.profile_read("cg", reset=True)
+    cg_out = m.sr_solve_cg(holder["O"], holder["e"], 1e-6, 0.01, tol=1e-8, max_iter=200)
+    ms_cg, _ = m.profile_read("cg", reset=True)
     m.profile(False)
+    d_cg, iters, resid = cg_out
+    o_bytes = holder["O"].numel() * holder["O"].element_size()
+    cg_rel = float((torch.linalg.norm(d_cg - holder["d"]) / torch.linalg.norm(holder["d"])).item())
+    cg = {"ms": ms_cg, "iterations": iters, "rel_residual": resid,
+          "ms_per_iteration": ms_cg / max(iters, 1),
+          "rel_diff_vs_sample_space": cg_rel, "bound": "hbm",
+          "achieved": 2.0 * o_bytes * iters / (ms_cg / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
+          "unit": "GB/s", "frac": 2.0 * o_bytes * iters / (ms_cg / 1e3) / 1e9 / PEAK_HBM_GBS,
+          "bytes_per_iteration": 2.0 * o_bytes}
     flops_gram = 8.0 * S * S * m.P / 2
     flops_chol = 8.0 * S ** 3 / 3
     pk_gram = 78.6 if w.precision == "fp64" else 157.3
@@ -447,6 +461,7 @@ def leg_sr(name="10x10_m400", S=32768, steps=1):
                                     "achieved": flops_chol / part["cholesky"] / 1e9,
                                     "peak": 78.6, "unit": "TFLOP/s",
                                     "frac": flops_chol / part["cholesky"] / 1e9 / 78.6},
+            "cg_parameter_space": cg,
             "dtheta_norm": float(holder["d"].abs().pow(2).sum().sqrt().item())}
 
 

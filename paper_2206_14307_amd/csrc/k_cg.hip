@@ -104,6 +104,97 @@ __global__ __launch_bounds__(kCgThreads) void cols_kernel(const RO* __restrict__
   part[2 * ((size_t)blockIdx.y * P + k) + 1] = qi;
 }
 
+// complex64 O: every P here is even (N even, M a multiple of 8), so a row's
+// column pairs are 16-byte aligned and one float4 load brings two columns.
+__global__ __launch_bounds__(kCgThreads) void rows2_kernel(const float* __restrict__ O, int64_t S,
+                                                           int64_t P, const double* __restrict__ v,
+                                                           const double* __restrict__ mv,
+                                                           double inv_sqrt_s,
+                                                           double* __restrict__ u) {
+  __shared__ double red[kCgRows][2][kCgThreads / 64];
+  const int64_t s0 = (int64_t)blockIdx.x * kCgRows;
+  const int64_t P2 = P / 2;
+  double ar[kCgRows], ai[kCgRows];
+#pragma unroll
+  for (int r = 0; r < kCgRows; ++r) ar[r] = ai[r] = 0.0;
+  for (int64_t k2 = threadIdx.x; k2 < P2; k2 += kCgThreads) {
+    const double4 vv = reinterpret_cast<const double4*>(v)[k2];
+#pragma unroll
+    for (int r = 0; r < kCgRows; ++r) {
+      if (s0 + r < S) {
+        const float4 o = reinterpret_cast<const float4*>(O + (size_t)(s0 + r) * P * 2)[k2];
+        ar[r] = fma((double)o.x, vv.x, fma(-(double)o.y, vv.y, ar[r]));
+        ai[r] = fma((double)o.x, vv.y, fma((double)o.y, vv.x, ai[r]));
+        ar[r] = fma((double)o.z, vv.z, fma(-(double)o.w, vv.w, ar[r]));
+        ai[r] = fma((double)o.z, vv.w, fma((double)o.w, vv.z, ai[r]));
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < kCgRows; ++r) {
+    const double sr = wave_sum(ar[r]), si = wave_sum(ai[r]);
+    if (lane == 0) {
+      red[r][0][wv] = sr;
+      red[r][1][wv] = si;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kCgRows && s0 + threadIdx.x < S) {
+    const int r = threadIdx.x;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int w = 0; w < kCgThreads / 64; ++w) {
+      sr += red[r][0][w];
+      si += red[r][1][w];
+    }
+    u[2 * (s0 + r)] = (sr - mv[0]) * inv_sqrt_s;
+    u[2 * (s0 + r) + 1] = (si - mv[1]) * inv_sqrt_s;
+  }
+}
+
+// part[slab][k] for the column pair (2 k2, 2 k2 + 1); rows of the slab four at
+// a time (independent loads in flight).
+__global__ __launch_bounds__(kCgThreads) void cols2_kernel(const float* __restrict__ O, int64_t S,
+                                                           int64_t P, int64_t slab,
+                                                           const double* __restrict__ u,
+                                                           double* __restrict__ part) {
+  const int64_t k2 = (int64_t)blockIdx.x * kCgThreads + threadIdx.x;
+  const int64_t sb = (int64_t)blockIdx.y * slab, se = std::min<int64_t>(S, sb + slab);
+  if (k2 >= P / 2) return;
+  double q0r = 0.0, q0i = 0.0, q1r = 0.0, q1i = 0.0;
+  int64_t s = sb;
+  for (; s + 4 <= se; s += 4) {
+    float4 o[4];
+    double2 uu[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      o[j] = reinterpret_cast<const float4*>(O + (size_t)(s + j) * P * 2)[k2];
+      uu[j] = u ? reinterpret_cast<const double2*>(u)[s + j] : make_double2(1.0, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      q0r = fma((double)o[j].x, uu[j].x, fma((double)o[j].y, uu[j].y, q0r));
+      q0i = fma((double)o[j].x, uu[j].y, fma(-(double)o[j].y, uu[j].x, q0i));
+      q1r = fma((double)o[j].z, uu[j].x, fma((double)o[j].w, uu[j].y, q1r));
+      q1i = fma((double)o[j].z, uu[j].y, fma(-(double)o[j].w, uu[j].x, q1i));
+    }
+  }
+  for (; s < se; ++s) {
+    const float4 o = reinterpret_cast<const float4*>(O + (size_t)s * P * 2)[k2];
+    const double2 uu = u ? reinterpret_cast<const double2*>(u)[s] : make_double2(1.0, 0.0);
+    q0r = fma((double)o.x, uu.x, fma((double)o.y, uu.y, q0r));
+    q0i = fma((double)o.x, uu.y, fma(-(double)o.y, uu.x, q0i));
+    q1r = fma((double)o.z, uu.x, fma((double)o.w, uu.y, q1r));
+    q1i = fma((double)o.z, uu.y, fma(-(double)o.w, uu.x, q1i));
+  }
+  double* dst = part + 2 * ((size_t)blockIdx.y * P + 2 * k2);
+  dst[0] = q0r;
+  dst[1] = q0i;
+  dst[2] = q1r;
+  dst[3] = q1i;
+}
+
 // Fixed-order block-wide sum (kVecThreads threads, one block).
 __device__ double vsum(double v, double* red) {
   const int t = threadIdx.x;
@@ -310,8 +401,13 @@ CgLayout cg_layout(const nqs_ctx* c, int64_t S) {
 template <typename RO>
 hipError_t cols_to(const RO* O, int64_t S, int64_t P, const CgLayout& L, const double* u,
                    double* part, hipStream_t st) {
-  const dim3 grid((unsigned)((P + kCgThreads - 1) / kCgThreads), (unsigned)L.nslab);
-  cols_kernel<RO><<<grid, kCgThreads, 0, st>>>(O, S, P, L.slab, u, part);
+  if constexpr (sizeof(RO) == 4) {
+    const dim3 grid((unsigned)((P / 2 + kCgThreads - 1) / kCgThreads), (unsigned)L.nslab);
+    cols2_kernel<<<grid, kCgThreads, 0, st>>>(O, S, P, L.slab, u, part);
+  } else {
+    const dim3 grid((unsigned)((P + kCgThreads - 1) / kCgThreads), (unsigned)L.nslab);
+    cols_kernel<RO><<<grid, kCgThreads, 0, st>>>(O, S, P, L.slab, u, part);
+  }
   return hipGetLastError();
 }
 
@@ -353,8 +449,12 @@ hipError_t cg_run(nqs_ctx* c, const RO* O, const double* eloc, int64_t S, double
   while (it < max_iter && bb > 0.0 && rr > tol * tol * bb) {
     // q = A p
     mdot_kernel<<<1, kVecThreads, 0, st>>>(m, p, P, scal);
-    rows_kernel<RO><<<(unsigned)((S + kCgRows - 1) / kCgRows), kCgThreads, 0, st>>>(O, S, P, p,
-                                                                                 scal, is, u);
+    if constexpr (sizeof(RO) == 4)
+      rows2_kernel<<<(unsigned)((S + kCgRows - 1) / kCgRows), kCgThreads, 0, st>>>(O, S, P, p,
+                                                                                scal, is, u);
+    else
+      rows_kernel<RO><<<(unsigned)((S + kCgRows - 1) / kCgRows), kCgThreads, 0, st>>>(O, S, P, p,
+                                                                                   scal, is, u);
     usum_kernel<<<1, kVecThreads, 0, st>>>(u, S, scal);
     if ((e = cols_to(O, S, P, L, u, part, st)) != hipSuccess) return e;
     slab_sum_kernel<<<ptiles, kCgThreads, 0, st>>>(part, (int)L.nslab, P, 1, is, m, scal + 2, 1.0,
@@ -391,6 +491,7 @@ extern "C" nqs_status nqs_sr_solve_cg(nqs_ctx* c, const void* O, const double* e
     return s;
   };
   if (S < 1 || !O || !eloc || !dtheta_out) return fail(NQS_ERR_ARG, "sr_solve_cg: bad arguments");
+  if (c->P % 2 != 0) return fail(NQS_ERR_ARG, "sr_solve_cg: P must be even");
   if (!(lambda >= 0.0) || !std::isfinite(lambda) || !std::isfinite(dtau) || !(tol >= 0.0) ||
       max_iter < 0)
     return fail(NQS_ERR_ARG, "sr_solve_cg: lambda >= 0, dtau finite, tol >= 0, max_iter >= 0");
