@@ -168,7 +168,7 @@ hipError_t prep_tables(nqs_ctx* c, hipStream_t st) {
 
 void free_all(nqs_ctx* c) {
   void* ptrs[] = {c->dev.perm, c->dev.perminv, c->dev.bonds, c->dev.bond_J, c->dev.bmap, c->dev.chi,
-                  c->dev.fmap, c->dev.frow, c->dev.binom,
+                  c->dev.fmap, c->dev.frow, c->dev.wmap, c->dev.wrow, c->dev.binom,
                   c->par.params, c->par.wfrag, c->par.bias, c->par.avec, c->par.Tpm,
                   c->par.F, c->par.Tpair, c->par.Fpair, c->par.Tdir, c->par.Urec, c->par.flag};
   for (void* p : ptrs)
@@ -303,6 +303,19 @@ nqs_status nqs_create(const nqs_model_desc* d, nqs_ctx** out) {
       fmap[i] = 2 * frow[c->geo.bmap[i] >> 1] + (c->geo.bmap[i] & 1);
     st = upload(c, &c->dev.frow, frow);
     if (st == NQS_OK) st = upload(c, &c->dev.fmap, fmap);
+  }
+  if (st == NQS_OK && eloc_wide_supported(c)) {
+    // wide kernel: chunk rows placed so that 16-image column blocks read
+    // (mostly) distinct bank groups
+    const int cap = nqs::wide_cap16(c->NB);
+    std::vector<int> addr = nqs::place_fused_rows(c->geo, nqs::kWideRow16, cap);
+    if (addr.empty())
+      for (int b = 0; b < c->NB; ++b) addr.push_back(b * nqs::kWideRow16);
+    std::vector<int32_t> wrow(addr.begin(), addr.end()), wmap((size_t)c->G * c->NB);
+    for (size_t i = 0; i < wmap.size(); ++i)
+      wmap[i] = 2 * (4 * addr[c->geo.bmap[i] >> 1]) + (c->geo.bmap[i] & 1);
+    st = upload(c, &c->dev.wrow, wrow);
+    if (st == NQS_OK) st = upload(c, &c->dev.wmap, wmap);
   }
   const size_t rs = real_size(c);
   const size_t frag_bytes = (size_t)c->n_htiles * c->nk * 64 * (c->prec == NQS_BF16X2 ? 16 : rs);

@@ -39,7 +39,9 @@ template <int N>
 struct WideCfg {
   static constexpr int NB = 4 * N;
   static constexpr int NSTG = (NB * kRP + 64 * kWideWaves - 1) / (64 * kWideWaves);  // float4 / thread
-  static constexpr size_t LDS = 2ull * NB * kTS * 4 + (size_t)kWideWaves * 16 * kXS * 4 + NB * 2 + 16;
+  static constexpr int CAP16 = wide_cap16(NB);        // staged table, 16-byte units
+  static constexpr size_t LDS = 2ull * CAP16 * 16 + (size_t)kWideWaves * 16 * kXS * 4 + NB * 2 +
+                                NB * 4 + 16;
 };
 
 template <int N, int PREC>
@@ -47,13 +49,16 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
     const int8_t* __restrict__ spins, int64_t S, const uint8_t* __restrict__ perm, int G, int K,
     int M, const typename ThetaTraits<PREC>::AFrag* __restrict__ wfrag,
     const float* __restrict__ bias, const float* __restrict__ avec,
-    const int32_t* __restrict__ bonds, const int32_t* __restrict__ bmap,
+    const int32_t* __restrict__ bonds, const int32_t* __restrict__ wmap,
+    const int32_t* __restrict__ wrow,
     const double* __restrict__ chi, const float* __restrict__ Tpm, const float* __restrict__ F,
     double* __restrict__ part) {
   using T = ThetaTraits<PREC>;
   using Cfg = WideCfg<N>;
   constexpr int NB = Cfg::NB, NK = nk_of<N, PREC>(), NSTG = Cfg::NSTG;
-  __shared__ __align__(16) float Tc[2][NB * kTS];
+  static_assert(kTS == 4 * kWideRow16, "row size of the placement");
+  __shared__ __align__(16) float Tc[2][Cfg::CAP16 * 4];
+  __shared__ int wrl[NB];                    // row starts in floats
   __shared__ __align__(16) float tx[kWideWaves][16 * kXS];
   __shared__ uint16_t list[NB];
   __shared__ int nc_s;
@@ -80,7 +85,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
 #define NQS_STG_ST(I, BUF)                                                               \
   if constexpr (I < NSTG) {                                                              \
     const int e = tid + 64 * kWideWaves * I;                                             \
-    if (e < NB * kRP) *reinterpret_cast<float4*>(&Tc[BUF][(e / kRP) * kTS + 4 * (e % kRP)]) = s##I; \
+    if (e < NB * kRP) *reinterpret_cast<float4*>(&Tc[BUF][wrl[e / kRP] + 4 * (e % kRP)]) = s##I; \
   }
 #define NQS_STAGE_LOAD(CH)                                                               \
   {                                                                                      \
@@ -92,8 +97,10 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
   {                                                                                      \
     NQS_STG_ST(0, BUF) NQS_STG_ST(1, BUF) NQS_STG_ST(2, BUF) NQS_STG_ST(3, BUF)          \
     NQS_STG_ST(4, BUF) NQS_STG_ST(5, BUF) NQS_STG_ST(6, BUF) NQS_STG_ST(7, BUF)          \
-    if (tid < NB) *reinterpret_cast<float4*>(&Tc[BUF][tid * kTS + 2 * kHC]) = sF;        \
+    if (tid < NB) *reinterpret_cast<float4*>(&Tc[BUF][wrl[tid] + 2 * kHC]) = sF;         \
   }
+  for (int idx = tid; idx < NB; idx += 64 * kWideWaves) wrl[idx] = 4 * wrow[idx];
+  __syncthreads();
   NQS_STAGE_LOAD(0)
   NQS_STAGE_STORE(0)
   int gc = 0;                                  // chunks processed by the workgroup so far
@@ -141,8 +148,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
         for (int jb = 0; jb < kWideBonds; ++jb) {
           const int ii = i0 + 4 * jb;
           const int e = ii < nc ? list[ii] : 0;   // padding entries use bond 0
-          const int v = bmap[(size_t)g * NB + (e & 0x7fff)];
-          offs[jb] = 2 * ((v >> 1) * kTS) + ((e >> 15) ^ (v & 1));
+          offs[jb] = wmap[(size_t)g * NB + (e & 0x7fff)] ^ (e >> 15);
         }
         float Pr[kWideBonds], Pi[kWideBonds];
         float lpr = 1.f, lpi = 0.f;
@@ -303,7 +309,8 @@ hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, h
   eloc_wide_kernel<N, PREC><<<(unsigned)blocks, 64 * kWideWaves, 0, st>>>(
       spins, S, c->dev.perm, c->G, c->K, c->M,
       (const typename ThetaTraits<PREC>::AFrag*)c->par.wfrag, (const float*)c->par.bias,
-      (const float*)c->par.avec, c->dev.bonds, c->dev.bmap, c->dev.chi, (const float*)c->par.Tpm,
+      (const float*)c->par.avec, c->dev.bonds, c->dev.wmap, c->dev.wrow, c->dev.chi,
+      (const float*)c->par.Tpm,
       (const float*)c->par.F, part);
   return hipGetLastError();
 }

@@ -39,6 +39,10 @@ constexpr int fused_row16(int K, int M, int real_bytes) {
 }
 constexpr int fused_cap16(int NB, int row16) { return NB * (row16 | 1) + 256; }
 std::vector<int> place_fused_rows(const Geometry& geo, int row16, int cap16);
+// Rows of the wide E_loc kernel's staged chunk table: 5 sixteen-byte units
+// (tanh D of 8 hidden units, then F_+, F_-), placed the same way.
+constexpr int kWideRow16 = 5;
+constexpr int wide_cap16(int NB) { return NB * kWideRow16 + 256; }
 
 // Binomial table of the Sz = 0 enumeration; false if C(N, N/2) overflows int64.
 bool sz0_binomials(int N, std::vector<uint64_t>& b, int64_t& count);
@@ -54,6 +58,8 @@ struct DeviceTables {
   uint64_t* binom = nullptr;      // [N+1][N+1] binomials (Sz = 0 enumeration), if C(N,N/2) fits
   int32_t* fmap = nullptr;        // [G][NB] fused kernel: 2 * (LDS row offset in reals) + flip
   int32_t* frow = nullptr;        // [NB]    fused kernel: LDS row offset in reals
+  int32_t* wmap = nullptr;        // [G][NB] wide kernel: 2 * (LDS row offset in floats) + flip
+  int32_t* wrow = nullptr;        // [NB]    wide kernel: LDS row start in 16-byte units
 };
 
 // Parameter-derived tables (rebuilt by nqs_set_params).  "R" is double for
