@@ -307,7 +307,7 @@ def leg_vmc(steps=3):
     m = NQS.from_workload(w)
     m.set_params(torch.from_numpy(draw_params(w).reshape(-1)))
     state = m.chain_init(torch.from_numpy(random_sz0_spins_fast(w.N, 1000, 77)).cuda())
-    nskip, t_s, t_v, rec = 0, [], [], None
+    nskip, t_s, t_v, t_c, rec, iters = 0, [], [], [], None, []
     for step in range(steps + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -315,16 +315,28 @@ def leg_vmc(steps=3):
                                seed=77)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        rec = m.vmc_step(sp, lam=1e-6, dtau=0.01)
+        # the same step with both solvers of Eq. (12), from the same parameters
+        p_before = m.get_params()
+        rec = m.vmc_step(sp, lam=1e-6, dtau=0.01, solver="cholesky")
         t2 = time.perf_counter()
+        m.set_params(p_before)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        rc = m.vmc_step(sp, lam=1e-6, dtau=0.01, solver="cg")
+        t4 = time.perf_counter()
         if step > 0:                                   # the first step carries the burn-in
             t_s.append(t1 - t0)
             t_v.append(t2 - t1)
+            t_c.append(t4 - t3)
+            iters.append(rc["solver_iters"])
         nskip = nskip_from_acceptance(float(acc.cpu().double().mean()))
     out = {"workload": "6x6_fp32_eloc", "samples_per_step": 10000, "n_skip": nskip,
-           "ms_sample": 1e3 * sum(t_s) / len(t_s), "ms_vmc_step": 1e3 * sum(t_v) / len(t_v),
+           "ms_sample": 1e3 * sum(t_s) / len(t_s),
+           "ms_vmc_step_cholesky": 1e3 * sum(t_v) / len(t_v),
+           "ms_vmc_step_cg": 1e3 * sum(t_c) / len(t_c), "cg_iterations": iters,
            "energy_per_site": rec["energy"] / w.N}
-    out["ms_per_training_step"] = out["ms_sample"] + out["ms_vmc_step"]
+    out["ms_per_training_step"] = out["ms_sample"] + min(out["ms_vmc_step_cholesky"],
+                                                          out["ms_vmc_step_cg"])
     w4 = dataclasses.replace(WORKLOADS["4x4_fp64_exact"], is_complex=True, J2=0.0)
     m4 = NQS.from_workload(w4)
     m4.set_params(torch.from_numpy(draw_params(w4).reshape(-1)))

@@ -96,6 +96,8 @@ typedef struct {
     double variance;            /* <|E_loc - <E_loc>|^2> */
     double error;               /* sqrt(variance / n) (no autocorrelation correction) */
     double dtheta_norm;         /* ||dtheta||_2 of the applied update */
+    int32_t solver_iters;       /* CG iterations (solver 1), 0 for solver 0 */
+    double solver_resid;        /* CG relative residual (solver 1), 0 for solver 0 */
 } nqs_vmc_stats;
 
 typedef struct nqs_ctx nqs_ctx;
@@ -209,7 +211,9 @@ nqs_status nqs_get_params(nqs_ctx* ctx, double* params_out_dev, hipStream_t stre
 /* One stochastic-reconfiguration training step (Sec. 3.2: Eq. (12) and the
  * update theta <- theta + dtheta after it) on S configurations, e.g. from
  * nqs_sample: E_loc (nqs_eloc), their FP64 statistics, O_k (nqs_grad),
- * dtheta = nqs_sr_solve(lambda, dtau); the context's parameters become
+ * dtheta from nqs_sr_solve (solver = 0: sample space, Cholesky) or from
+ * nqs_sr_solve_cg (solver = 1: parameter-space CG as in Sec. 3.4, relative
+ * residual 1e-8, at most 2000 iterations); the context's parameters become
  * theta + dtheta (the imaginary part of dtheta is dropped when
  * real_params = 1, for real RBMs) and the tables are rebuilt.  *out
  * describes the parameters before the update.  Workspace:
@@ -217,8 +221,8 @@ nqs_status nqs_get_params(nqs_ctx* ctx, double* params_out_dev, hipStream_t stre
  * those of the three calls; NQS_ERR_NONFINITE (parameters unchanged) if
  * theta + dtheta is not finite. */
 nqs_status nqs_vmc_step(nqs_ctx* ctx, const int8_t* spins, int64_t S, double lambda, double dtau,
-                        int real_params, nqs_vmc_stats* out, void* ws, size_t ws_bytes,
-                        hipStream_t stream);
+                        int real_params, int solver, nqs_vmc_stats* out, void* ws,
+                        size_t ws_bytes, hipStream_t stream);
 
 /* Pack initial configurations into chain states: chain_state [n][4] uint64
  * = {spin bits 0..63, spin bits 64..127, proposal counter = 0, chain id}

@@ -215,6 +215,7 @@ VmcCarve vmc_carve(const nqs_ctx* c, int64_t S) {
   size_t sub = plan(c, NQS_OP_ELOC, S, nullptr).bytes;
   sub = std::max(sub, plan(c, NQS_OP_GRAD, S, nullptr).bytes);
   sub = std::max(sub, sr_workspace_bytes(c, S));
+  sub = std::max(sub, cg_workspace_bytes(c, S));
   v.bytes = off + align_up(std::max<size_t>(sub, 1));
   return v;
 }
@@ -389,10 +390,11 @@ nqs_status nqs_get_params(nqs_ctx* c, double* params_out, hipStream_t st) {
 }
 
 nqs_status nqs_vmc_step(nqs_ctx* c, const int8_t* spins, int64_t S, double lambda, double dtau,
-                        int real_params, nqs_vmc_stats* out, void* ws, size_t ws_bytes,
-                        hipStream_t st) {
+                        int real_params, int solver, nqs_vmc_stats* out, void* ws,
+                        size_t ws_bytes, hipStream_t st) {
   if (!c) return NQS_ERR_ARG;
   if (S < 1 || !spins || !out) return fail(c, NQS_ERR_ARG, "vmc_step: needs S >= 1, spins, out");
+  if (solver != 0 && solver != 1) return fail(c, NQS_ERR_ARG, "vmc_step: solver must be 0 or 1");
   const VmcCarve v = vmc_carve(c, S);
   if (!ws || ws_bytes < v.bytes)
     return fail(c, NQS_ERR_ARG, "vmc_step: workspace too small: need " + std::to_string(v.bytes));
@@ -409,7 +411,12 @@ nqs_status nqs_vmc_step(nqs_ctx* c, const int8_t* spins, int64_t S, double lambd
   hipError_t e = launch_energy_stats(eloc, S, stats, st);
   if (e != hipSuccess) return hip_fail(c, e, "energy statistics");
   if ((s = nqs_grad(c, spins, S, O, nullptr, sub, sub_bytes, st)) != NQS_OK) return s;
-  if ((s = nqs_sr_solve(c, O, eloc, S, lambda, dtau, dth, sub, sub_bytes, st)) != NQS_OK) return s;
+  int iters = 0;
+  double resid = 0.0;
+  s = solver == 0 ? nqs_sr_solve(c, O, eloc, S, lambda, dtau, dth, sub, sub_bytes, st)
+                  : nqs_sr_solve_cg(c, O, eloc, S, lambda, dtau, 1e-8, 2000, dth, &iters, &resid,
+                                    sub, sub_bytes, st);
+  if (s != NQS_OK) return s;
   if ((e = launch_params_step(c->par.params, dth, c->P, real_params ? 0 : 1, next, stats, st)) !=
       hipSuccess)
     return hip_fail(c, e, "parameter step");
@@ -423,6 +430,8 @@ nqs_status nqs_vmc_step(nqs_ctx* c, const int8_t* spins, int64_t S, double lambd
   out->variance = h[2];
   out->error = std::sqrt(h[2] / (double)S);
   out->dtheta_norm = h[3];
+  out->solver_iters = iters;
+  out->solver_resid = resid;
   if (h[4] != 0.0) return fail(c, NQS_ERR_NONFINITE, "vmc_step: theta + dtheta is not finite");
   if ((e = hipMemcpyAsync(c->par.params, next, (size_t)c->P * 16, hipMemcpyDeviceToDevice, st)) !=
       hipSuccess)

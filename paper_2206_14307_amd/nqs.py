@@ -45,7 +45,8 @@ class Moments(C.Structure):
 
 class VmcStats(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, C.c_double) for k in (
-        "energy", "energy_im", "variance", "error", "dtheta_norm")]
+        "energy", "energy_im", "variance", "error", "dtheta_norm")] + [
+        ("solver_iters", C.c_int32), ("solver_resid", C.c_double)]
 
 
 class NQSError(RuntimeError):
@@ -86,8 +87,8 @@ def load_library(path: str = LIB_PATH):
         "nqs_get_params": ([vp, vp, vp], C.c_int),
         "nqs_sr_solve_cg": ([vp, vp, vp, i64, dbl, dbl, dbl, C.c_int, vp, C.POINTER(C.c_int),
                              C.POINTER(dbl), vp, C.c_size_t, vp], C.c_int),
-        "nqs_vmc_step": ([vp, vp, i64, dbl, dbl, C.c_int, C.POINTER(VmcStats), vp, C.c_size_t, vp],
-                         C.c_int),
+        "nqs_vmc_step": ([vp, vp, i64, dbl, dbl, C.c_int, C.c_int, C.POINTER(VmcStats), vp,
+                          C.c_size_t, vp], C.c_int),
         "nqs_profile_enable": ([vp, C.c_int], C.c_int),
         "nqs_profile_read": ([vp, C.c_int, C.POINTER(dbl), C.POINTER(i64), C.c_int], C.c_int),
         "nqs_status_str": ([C.c_int], C.c_char_p),
@@ -188,15 +189,17 @@ class NQS:
                     "nqs_get_params")
         return out
 
-    def vmc_step(self, spins, lam=1e-6, dtau=0.01, real_params=False):
+    def vmc_step(self, spins, lam=1e-6, dtau=0.01, real_params=False, solver="cholesky"):
         """One SR training step on the configurations (nqs_vmc_step): returns the
-        energy statistics of the parameters before the update."""
+        energy statistics of the parameters before the update.  solver:
+        "cholesky" (sample space) or "cg" (parameter space)."""
+        code = {"cholesky": 0, "cg": 1}[solver]
         sp = self._spins(spins)
         S = sp.shape[0]
         ws = self.workspace("vmc", S)
         st = VmcStats()
         self._check(self.lib.nqs_vmc_step(self._ctx, _ptr(sp), S, float(lam), float(dtau),
-                                          int(bool(real_params)), C.byref(st), _ptr(ws),
+                                          int(bool(real_params)), code, C.byref(st), _ptr(ws),
                                           ws.numel(), _stream()), "nqs_vmc_step")
         return {k: getattr(st, k) for k, _ in VmcStats._fields_}
 

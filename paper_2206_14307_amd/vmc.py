@@ -49,7 +49,7 @@ class DtauSchedule:
 
 
 def train(model, init_spins, steps, n_per_chain, dtau=0.02, lam=1e-6, seed=0, n_burn=None,
-          real_params=False, window=10, dtau_min=5e-4, callback=None):
+          real_params=False, window=10, dtau_min=5e-4, solver="cholesky", callback=None):
     """Run `steps` SR steps with len(init_spins) chains and n_per_chain
     samples per chain and step.  Returns the per-step records (energy
     statistics before each update, N_skip, acceptance, dtau)."""
@@ -63,7 +63,8 @@ def train(model, init_spins, steps, n_per_chain, dtau=0.02, lam=1e-6, seed=0, n_
                                    n_burn=n_burn if step == 0 else 0, seed=seed)
         used = int(ns.item()) if nskip == 0 else nskip
         r = float(acc.cpu().double().mean())
-        stats = model.vmc_step(sp, lam=lam, dtau=sched.dtau, real_params=real_params)
+        stats = model.vmc_step(sp, lam=lam, dtau=sched.dtau, real_params=real_params,
+                               solver=solver)
         rec = dict(stats, step=step, n_skip=used, acceptance=r, dtau=sched.dtau)
         history.append(rec)
         if callback is not None:

@@ -27,19 +27,21 @@ def test_params_round_trip():
     assert np.array_equal(m.get_params().cpu().numpy(), p)
 
 
-@pytest.mark.parametrize("lam", [1e-3, 1e-6])
-def test_vmc_step_matches_oracle(lam):
+@pytest.mark.parametrize("lam,solver,tol", [(1e-3, "cholesky", 1e-8), (1e-6, "cholesky", 1e-6),
+                                            (1e-3, "cg", 1e-6)])
+def test_vmc_step_matches_oracle(lam, solver, tol):
     """Statistics before the update = the oracle's mean and centred variance
     of E_loc; the new parameters = theta + the oracle's sample-space dtheta
     (computed from its own E_loc and O_k).  1e-8 relative on dtheta at the
     well-conditioned ridge, 1e-6 at the paper's 1e-6 (the GPU's O and E_loc
-    agree with the oracle's to 1e-10 and the solve amplifies that)."""
+    agree with the oracle's to 1e-10 and the solve amplifies that); with CG
+    (relative residual 1e-8) 1e-6 at the well-conditioned ridge."""
     w = dataclasses.replace(WORKLOADS["4x4_fp64_exact"], is_complex=True)
     p0 = stress_params(w, 0.1, 3).reshape(-1)
     om = oracle.Model.from_workload(w)
     sp = random_sz0_spins(w.N, 300, 4)
     m = make(w, p0)
-    st = m.vmc_step(torch.from_numpy(sp).cuda(), lam=lam, dtau=0.02)
+    st = m.vmc_step(torch.from_numpy(sp).cuda(), lam=lam, dtau=0.02, solver=solver)
     e1 = oracle.eloc_direct(om, p0, sp)
     O = oracle.logderiv(om, p0, sp)
     ref = oracle.sr_sample_space(O, e1, lam, 0.02)
@@ -49,7 +51,7 @@ def test_vmc_step_matches_oracle(lam):
     assert st["energy_im"] == pytest.approx(e1.imag.mean(), abs=1e-10)
     assert st["variance"] == pytest.approx(np.mean(np.abs(e1 - e1.mean()) ** 2), rel=1e-9)
     assert st["dtheta_norm"] == pytest.approx(np.linalg.norm(ref), rel=1e-6)
-    tol = 1e-8 if lam >= 1e-3 else 1e-6
+    assert (st["solver_iters"] > 0) == (solver == "cg")
     assert np.linalg.norm(got - ref) < tol * np.linalg.norm(ref)
 
 
@@ -70,8 +72,10 @@ def test_real_parameters_stay_real_and_failed_steps_change_nothing():
     assert np.array_equal(m.get_params().cpu().numpy(), p1)
 
 
-@pytest.mark.parametrize("J2,steps,gate", [(0.0, 200, 1e-4), (0.5, 300, 1e-2)])
-def test_training_4x4_reaches_exact_energy(J2, steps, gate):
+@pytest.mark.parametrize("J2,steps,gate,solver", [(0.0, 200, 1e-4, "cholesky"),
+                                                  (0.5, 300, 1e-2, "cholesky"),
+                                                  (0.0, 200, 1e-4, "cg")])
+def test_training_4x4_reaches_exact_energy(J2, steps, gate, solver):
     """SR training of the complex M = 16 RBM from N(0, 0.01) on the 4x4
     lattice (256 chains x 8 samples per step, dtau = 0.05, lambda = 1e-6):
     the exact energy of the trained state (the whole Sz = 0 sector with Born
@@ -81,7 +85,7 @@ def test_training_4x4_reaches_exact_energy(J2, steps, gate):
     w = dataclasses.replace(WORKLOADS["4x4_fp64_exact"], is_complex=True, J2=J2)
     m = make(w, draw_params(w))
     init = torch.from_numpy(random_sz0_spins(w.N, 256, 3)).cuda()
-    hist = train(m, init, steps=steps, n_per_chain=8, dtau=0.05)
+    hist = train(m, init, steps=steps, n_per_chain=8, dtau=0.05, solver=solver)
     assert len(hist) == steps and hist[-1]["energy"] < hist[0]["energy"]
     res, _ = m.lanczos_moments(m.enumerate_sz0(), exact=True)
     e0 = oracle.ground_state(oracle.Model.from_workload(w))[0][0]
