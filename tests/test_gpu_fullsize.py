@@ -1,0 +1,71 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times: one launch over all configurations, checked against the
+oracle on sampled rows (the oracle re-evaluates psi at every connected
+configuration, seconds per row at 8x8 and 10x10).
+
+* 6x6 Lanczos workload, 8192 configurations: e1 and e2 of nqs_lanczos_moments;
+* 8x8 K = 4 x M = 256, 16 384 configurations: nqs_eloc with FP32 and split-BF16 theta;
+* 10x10 M = 400, 32 768 configurations: nqs_eloc, nqs_grad and nqs_logpsi (split BF16).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import TOL, max_logpsi_err, max_rel_err, max_row_rel_err, nonzero_rows
+from workloads import WORKLOADS, draw_params
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(name, **over):
+    from paper_2206_14307_amd import NQS
+    w = dataclasses.replace(WORKLOADS[name], **over)
+    p = draw_params(w)
+    m = NQS.from_workload(w)
+    m.set_params(torch.from_numpy(p.reshape(-1)))
+    S = w.n_chains * w.n_per_chain
+    rng = np.random.default_rng(31)
+    half = np.r_[np.ones(w.N // 2, np.int8), -np.ones(w.N // 2, np.int8)]
+    sp = rng.permuted(np.tile(half, (S, 1)), axis=1)
+    rows = np.r_[0, S - 1, rng.choice(S - 2, 2, replace=False) + 1]
+    return w, p, m, sp, rows, oracle.Model.from_workload(w)
+
+
+def test_lanczos_moments_full_size():
+    w, p, m, sp, rows, om = _setup("6x6_fp32_lanczos")
+    rows = rows[:2]
+    res, e12 = m.lanczos_moments(torch.from_numpy(sp).cuda())
+    e12 = e12.cpu().numpy()
+    assert res["n"] == len(sp)
+    assert max_rel_err(e12[rows, 0], oracle.eloc_direct(om, p, sp[rows])) < TOL[w.precision]
+    assert max_rel_err(e12[rows, 1], oracle.e2_direct(om, p, sp[rows])) < TOL[w.precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x2"])
+def test_eloc_8x8_full_size(precision):
+    w, p, m, sp, rows, om = _setup("8x8_k4_m256", precision=precision)
+    rows = rows[nonzero_rows(om, p, sp[rows])][:3]
+    lp, el = m.eloc(torch.from_numpy(sp).cuda())
+    tol = TOL[w.precision]
+    assert max_logpsi_err(lp.cpu().numpy()[rows], oracle.logpsi(om, p, sp[rows])) < tol
+    assert max_rel_err(el.cpu().numpy()[rows], oracle.eloc_direct(om, p, sp[rows])) < tol
+
+
+def test_eloc_grad_logpsi_10x10_full_size():
+    w, p, m, sp, rows, om = _setup("10x10_m400")
+    rows = rows[:2]
+    tol = TOL[w.precision]
+    spt = torch.from_numpy(sp).cuda()
+    lp, el = m.eloc(spt)
+    assert max_rel_err(el.cpu().numpy()[rows], oracle.eloc_direct(om, p, sp[rows])) < tol
+    ref_lp = oracle.logpsi(om, p, sp[rows])
+    assert max_logpsi_err(lp.cpu().numpy()[rows], ref_lp) < tol
+    assert max_logpsi_err(m.logpsi(spt).cpu().numpy()[rows], ref_lp) < tol
+    del lp, el
+    O = m.grad(spt)
+    Os = O[torch.from_numpy(rows).cuda()].cpu().numpy()
+    del O
+    assert max_row_rel_err(Os, oracle.logderiv(om, p, sp[rows])) < tol
