@@ -17,10 +17,10 @@ from .model import Model
 from .wavefunction import log2cosh, logpsi_s, logpsi, images, image_weights
 from . import wavefunction, sampler
 from .hamiltonian import (
-    diag_energy, eloc_direct, e2_direct, sector_basis, hamiltonian_sector,
+    diag_energy, eloc_direct, e2_direct, e3_direct, sector_basis, hamiltonian_sector,
     hamiltonian_kron, ground_state, total_spin_sq_sector, flip_bond,
 )
-from .lanczos import moments, lanczos_p1, lanczos_p1_explicit
+from .lanczos import moments, lanczos_p1, lanczos_p1_explicit, lanczos_p2, lanczos_p2_explicit
 from .grad import logderiv, logderiv_fd
 from .sr import sr_param_space, sr_sample_space
 from .philox import philox4x64_10, uniform53
@@ -30,9 +30,9 @@ from .observables import momenta, correlations, structure_factor
 __all__ = [
     "Lattice", "C4V_CHARACTERS", "POINT_OPS", "POINT_CLASS", "Model",
     "log2cosh", "logpsi_s", "logpsi", "images",
-    "diag_energy", "eloc_direct", "e2_direct", "sector_basis", "hamiltonian_sector",
+    "diag_energy", "eloc_direct", "e2_direct", "e3_direct", "sector_basis", "hamiltonian_sector",
     "hamiltonian_kron", "ground_state", "total_spin_sq_sector", "flip_bond",
-    "moments", "lanczos_p1", "lanczos_p1_explicit",
+    "moments", "lanczos_p1", "lanczos_p1_explicit", "lanczos_p2", "lanczos_p2_explicit",
     "logderiv", "logderiv_fd", "sr_param_space", "sr_sample_space",
     "philox4x64_10", "uniform53", "exchange_metropolis",
     "momenta", "correlations", "structure_factor",

@@ -73,6 +73,23 @@ def e2_direct(model, params, spins):
     return diag_energy(model, spins) * e1 + off
 
 
+def e3_direct(model, params, spins):
+    """e3(sigma) = <sigma|H^3|psi>/<sigma|psi>, one hop further than e2:
+    H_{sigma sigma} e2(sigma) + sum_b (J_b/2) psi(sigma^b)/psi(sigma) e2(sigma^b),
+    with e2 at every neighbour from e2_direct (the <H^4>, <H^5> of a p = 2
+    Lanczos step, Sec. 3.3, need it)."""
+    spins = np.atleast_2d(np.asarray(spins))
+    lp = logpsi(model, params, spins)
+    e2 = e2_direct(model, params, spins)
+    s_idx, b_idx, conn = _connected(model, spins)
+    lp_conn = logpsi(model, params, conn)
+    e2_conn = e2_direct(model, params, conn)
+    terms = 0.5 * model.bond_J[b_idx] * np.exp(lp_conn - lp[s_idx]) * e2_conn
+    off = np.zeros(spins.shape[0], np.complex128)
+    np.add.at(off, s_idx, terms)
+    return diag_energy(model, spins) * e2 + off
+
+
 # ---------------------------------------------------------------- the sector
 
 def sector_basis(N):

@@ -15,6 +15,24 @@ Readings of the passage:
 * v = 0 (an exact eigenstate): E_p1 = <H>, alpha = 0, flagged degenerate.
   "Zero" means c2 <= (8 eps max(|h1|, 1))^2 with eps the FP64 unit roundoff
   2^-53: below that the centred variance is rounding noise of h1 itself.
+
+p = 2 (Sec. 3.3, Eq. (19) with p = 2), readings:
+* The coefficients beta_1, beta_2 of Psi_2 = (1 + beta_1 H + beta_2 H^2) psi are
+  those of the lowest eigenvector of H restricted to the Krylov space
+  span{psi, H psi, H^2 psi} (the p = 1 step is the same construction on
+  span{psi, H psi}); E_p2 is its lowest Ritz value.
+* In the basis u_i = ((H - h1)/v)^i psi the Gram and Hamiltonian matrices are
+  Hankel in the centred moments mu_k = <(H - h1)^k>: B_ij = mu_{i+j}/v^{i+j},
+  A_ij = mu_{i+j+1}/v^{i+j}, E_p2 = h1 + v lambda_min(A, B).  Each mu_k is
+  estimated with the balanced split mu_k = Re<conj(d_{floor(k/2)}) d_{ceil(k/2)}>
+  of the local values d_1 = e1 - h1, d_2 = e2 - 2 h1 e1 + h1^2,
+  d_3 = e3 - 3 h1 e2 + 3 h1^2 e1 - h1^3 (so mu_2 = c2, mu_3 = c3 as for p = 1,
+  mu_4 = <|d_2|^2>, mu_5 = Re<conj(d_2) d_3>); with exact weights every split
+  gives the exact moment.
+* The scaled Gram determinant is delta = mu_4/v^4 - r^2 - 1.  delta <=
+  64 eps max(mu_4/v^4, 1) means the Krylov space has dimension 2 (psi spans
+  two eigenvalues) or the Monte-Carlo Hankel matrix is not positive definite:
+  E_p2 = E_p1, beta_2 = 0, flagged degenerate.
 """
 from __future__ import annotations
 
@@ -34,11 +52,12 @@ def _fsum_r(x, w):
     return math.fsum(np.asarray(x) * w) / math.fsum(w)
 
 
-def moments(e1, e2=None, weights=None):
+def moments(e1, e2=None, weights=None, e3=None):
     """Two-pass FP64 moments with exactly rounded sums (math.fsum).
 
     weights: None for Monte-Carlo mode (uniform 1/S), else the exact Born
-    weights p_sigma = |psi|^2 / sum |psi|^2 (Sec. 3.2, Eq. (9))."""
+    weights p_sigma = |psi|^2 / sum |psi|^2 (Sec. 3.2, Eq. (9)).
+    e3 (with e2): adds h4, h5, mu4, mu5 and the p = 2 energy."""
     e1 = np.asarray(e1, np.complex128)
     n = len(e1)
     w = np.ones(n) if weights is None else np.asarray(weights, np.float64)
@@ -56,6 +75,14 @@ def moments(e1, e2=None, weights=None):
         d2 = e2 - 2.0 * h1 * e1 + h1 * h1
         out["c3"] = _fsum_c(np.conj(d1) * d2, w).real
         out.update(lanczos_p1(h1, out["c2"], out["c3"]))
+        if e3 is not None:
+            e3 = np.asarray(e3, np.complex128)
+            d3 = e3 - 3.0 * h1 * e2 + 3.0 * h1 * h1 * e1 - h1 ** 3
+            out["h4"] = _fsum_r(np.abs(e2) ** 2, w)
+            out["h5"] = _fsum_c(np.conj(e2) * e3, w).real
+            out["mu4"] = _fsum_r(np.abs(d2) ** 2, w)
+            out["mu5"] = _fsum_c(np.conj(d2) * d3, w).real
+            out.update(lanczos_p2(h1, out["c2"], out["c3"], out["mu4"], out["mu5"]))
     return out
 
 
@@ -82,3 +109,43 @@ def lanczos_p1_explicit(H, psi):
     A = 0.5 * (A + A.conj().T)
     B = 0.5 * (B + B.conj().T)
     return float(sla.eigh(A, B, eigvals_only=True)[0])
+
+
+def lanczos_p2(h1, mu2, mu3, mu4, mu5):
+    """Lowest Ritz value of H in span{psi, H psi, H^2 psi} from the centred
+    moments (Sec. 3.3, Eq. (19) with p = 2; readings above): the generalised
+    3x3 Hankel eigenproblem solved with scipy's eigh, and the coefficients
+    beta_1, beta_2 of Psi_2 = (1 + beta_1 H + beta_2 H^2) psi."""
+    p1 = lanczos_p1(h1, mu2, mu3)
+    out = {"e_p2": p1["e_p1"], "beta1": 0.0, "beta2": 0.0, "degenerate2": True}
+    if p1["degenerate"]:
+        return out
+    v, alpha = p1["v"], p1["alpha"]
+    # p = 1 fallback: Psi_1 = psi + alpha (H - h1) psi / v
+    c0, c1 = 1.0 - alpha * h1 / v, alpha / v
+    out["beta1"] = c1 / c0
+    m = [1.0, 0.0, 1.0, mu3 / v ** 3, mu4 / v ** 4, mu5 / v ** 5]
+    delta = m[4] - m[3] ** 2 - 1.0
+    if not delta > 64.0 * 2.0 ** -53 * max(m[4], 1.0):
+        return out
+    B = np.array([[m[i + j] for j in range(3)] for i in range(3)])
+    A = np.array([[m[i + j + 1] for j in range(3)] for i in range(3)])
+    lam, X = sla.eigh(A, B)
+    x = X[:, 0]
+    # x0 + x1 K + x2 K^2 with K = (H - h1)/v, expanded in powers of H
+    c0 = x[0] - x[1] * h1 / v + x[2] * h1 * h1 / (v * v)
+    c1 = x[1] / v - 2.0 * x[2] * h1 / (v * v)
+    c2 = x[2] / (v * v)
+    return {"e_p2": h1 + v * float(lam[0]), "beta1": c1 / c0, "beta2": c2 / c0,
+            "degenerate2": False}
+
+
+def lanczos_p2_explicit(H, psi):
+    """Lowest Ritz value of H in span{psi, H psi, H^2 psi} from explicit sector
+    vectors, orthonormalised by QR (pins the moment route of lanczos_p2)."""
+    u = np.stack([psi, H @ psi, H @ (H @ psi)], axis=1)
+    Q, _ = np.linalg.qr(u)
+    Hq = np.stack([H @ Q[:, k] for k in range(3)], axis=1)
+    A = Q.conj().T @ Hq
+    A = 0.5 * (A + A.conj().T)
+    return float(np.linalg.eigvalsh(A)[0])
