@@ -217,6 +217,34 @@ def timed(fn, steps, warmup):
     return ev0.elapsed_time(ev1) / steps
 
 
+def twohop_hops(spins, bonds):
+    """Exchange factors per image and hidden unit of e1 + e2 over a set of
+    configurations: one-hop n_c(s) plus two-hop sum_{b1} n_c(s^{b1})."""
+    hops = 0
+    for s0 in range(0, len(spins), 512):
+        x = spins[s0:s0 + 512].astype(np.int16)
+        anti = x[:, bonds[:, 0]] != x[:, bonds[:, 1]]
+        hops += int(anti.sum())
+        for b, (i, j) in enumerate(bonds):
+            rows = np.nonzero(anti[:, b])[0]
+            if rows.size:
+                y = x[rows].copy()
+                y[:, [i, j]] = -y[:, [i, j]]
+                hops += int((y[:, bonds[:, 0]] != y[:, bonds[:, 1]]).sum())
+    return hops
+
+
+def neighbours(spins, bonds):
+    """All exchange neighbours s^b (antiparallel bonds b) of the configurations."""
+    out = []
+    for i, j in bonds:
+        rows = np.nonzero(spins[:, i] != spins[:, j])[0]
+        y = spins[rows].copy()
+        y[:, [i, j]] = y[:, [j, i]]
+        out.append(y)
+    return np.concatenate(out)
+
+
 def leg_lanczos(steps=2):
     """Two-hop e2 + FP64 moments on the 6x6 Lanczos workload (8192 samples)."""
     import torch
@@ -231,23 +259,49 @@ def leg_lanczos(steps=2):
     ms = timed(lambda: res.update(m.lanczos_moments(sp, exact=False, want_e1e2=False)[0]), steps, 1)
     # exact factor count: one-hop n_c(s) plus two-hop sum_{b1} n_c(s^{b1}), times G K M
     bonds = square_bonds(w.L)
-    spins = sp.cpu().numpy()
-    hops = 0
-    for s0 in range(0, S, 512):
-        x = spins[s0:s0 + 512].astype(np.int16)
-        anti = x[:, bonds[:, 0]] != x[:, bonds[:, 1]]
-        hops += int(anti.sum())
-        for b, (i, j) in enumerate(bonds):
-            rows = np.nonzero(anti[:, b])[0]
-            if rows.size:
-                y = x[rows].copy()
-                y[:, [i, j]] = -y[:, [i, j]]
-                hops += int((y[:, bonds[:, 0]] != y[:, bonds[:, 1]]).sum())
+    hops = twohop_hops(sp.cpu().numpy(), bonds)
     factors = float(hops) * w.G * w.n_rbm * w.n_hidden
     flops = 13.0 * factors
     return {"workload": w.name, "S": S, "ms": ms,
             "configs_per_s": S / (ms / 1e3), "h1_per_site": res["h1"] / w.N,
             "e_p1_per_site": res["e_p1"] / w.N, "factors": factors,
+            "roofline": {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12, "peak": 157.3,
+                         "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / 1e12 / 157.3,
+                         "flops_per_factor": 13}}
+
+
+def leg_lanczos2(S=256, steps=1):
+    """p = 2 Lanczos (e1, e2, e3 + fifth-order moments + 3x3 Krylov solve) on
+    the first S configurations of the 6x6 Lanczos workload's random set."""
+    import torch
+    from paper_2206_14307_amd import NQS
+    from workloads import WORKLOADS, draw_params, random_sz0_spins_fast
+    w = WORKLOADS["6x6_fp32_lanczos"]
+    m = NQS.from_workload(w)
+    m.set_params(torch.from_numpy(draw_params(w).reshape(-1)))
+    spins = random_sz0_spins_fast(w.N, w.n_chains * w.n_per_chain, 3003)[:S]
+    sp = torch.from_numpy(spins).cuda()
+    res = {}
+    ms = timed(lambda: res.update(m.lanczos_moments_p2(sp, exact=False, want_e123=False)[0]),
+               steps, 1)
+    # one more call with per-kernel events: where the time goes
+    names = ("theta", "lse", "eloc_bonds", "eloc_finish", "twohop", "twohop_finish", "hop3")
+    m.profile(True)
+    for k in names:
+        m.profile_read(k, reset=True)
+    m.lanczos_moments_p2(sp, exact=False, want_e123=False)
+    split = {k: round(m.profile_read(k, reset=True)[0], 3) for k in names}
+    m.profile(False)
+    bonds = square_bonds(w.L)
+    nb = neighbours(spins, bonds)
+    hops = twohop_hops(spins, bonds) + twohop_hops(nb, bonds)
+    factors = float(hops) * w.G * w.n_rbm * w.n_hidden
+    flops = 13.0 * factors
+    return {"workload": w.name, "S": S, "neighbour_configs": int(len(nb)), "ms": ms,
+            "configs_per_s": S / (ms / 1e3), "h1_per_site": res["h1"] / w.N,
+            "e_p1_per_site": res["e_p1"] / w.N, "e_p2_per_site": res["e_p2"] / w.N,
+            "degenerate": res["degenerate"], "factors": factors,
+            "kernel_ms": split,
             "roofline": {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12, "peak": 157.3,
                          "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / 1e12 / 157.3,
                          "flops_per_factor": 13}}
@@ -485,7 +539,7 @@ def main():
     ap.add_argument("--workload", default="6x6_fp32_eloc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true")
-    ap.add_argument("--legs", default="grad,logpsi,sq,vmc,lanczos,precision,sr",
+    ap.add_argument("--legs", default="grad,logpsi,sq,vmc,lanczos,lanczos2,precision,sr",
                     help="comma-separated subset of the extra legs to run")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (HBM counter calibration)")
@@ -625,6 +679,9 @@ def main():
     if "lanczos" in which:
         legs["lanczos_two_hop"] = leg_lanczos()
         log(f"lanczos leg: {legs['lanczos_two_hop']['ms']:.2f} ms")
+    if "lanczos2" in which:
+        legs["lanczos_p2"] = leg_lanczos2()
+        log(f"lanczos p=2 leg: {legs['lanczos_p2']['ms']:.1f} ms")
     if "precision" in which:
         legs["bf16x2_vs_fp32_8x8"] = leg_precision(
             "8x8_k4_m256", None if refs is None or not refs["extra"] else refs["extra"][0])

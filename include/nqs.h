@@ -63,7 +63,7 @@ typedef enum {
 typedef enum {
     NQS_OP_LOGPSI = 0, NQS_OP_ELOC = 1, NQS_OP_MOMENTS = 2,
     NQS_OP_GRAD = 3, NQS_OP_SR = 4, NQS_OP_SAMPLE = 5, NQS_OP_SQ = 6, NQS_OP_VMC = 7,
-    NQS_OP_CG = 8
+    NQS_OP_CG = 8, NQS_OP_MOMENTS2 = 9
 } nqs_op;
 
 typedef struct {
@@ -88,6 +88,24 @@ typedef struct {
     double h1, h1_im, h2, h2_alt, h3, c2, c3, v, r, alpha, e_p1, h1_err;
     int32_t degenerate;
 } nqs_moments;
+
+/* Moments to fifth order and the p = 2 Lanczos energy (Sec. 3.3, Eq. (19)
+ * with p = 2).  All FP64.  With d1 = e1 - h1, d2 = e2 - 2 h1 e1 + h1^2,
+ * d3 = e3 - 3 h1 e2 + 3 h1^2 e1 - h1^3: h4 = <|e2|^2>, h5 = Re<conj(e2) e3>,
+ * mu4 = <|d2|^2>, mu5 = Re<conj(d2) d3>.  e_p2 is the lowest eigenvalue of H
+ * in span{psi, H psi, H^2 psi}: the generalised 3x3 Hankel problem
+ * A_ij = mu_{i+j+1}/v^{i+j}, B_ij = mu_{i+j}/v^{i+j} (mu_0 = 1, mu_1 = 0,
+ * mu_2 = c2, mu_3 = c3), E = h1 + v lambda_min.  Psi_2 = (1 + beta1 H +
+ * beta2 H^2) psi is its eigenvector.  degenerate: the scaled Gram determinant
+ * mu4/v^4 - r^2 - 1 is <= 64 eps max(mu4/v^4, 1) (Krylov dimension 2, or a
+ * Monte-Carlo Hankel matrix that is not positive definite) or the p = 1 step
+ * is degenerate: then e_p2 = e_p1, beta2 = 0 (and beta1 is the p = 1 one). */
+typedef struct {
+    nqs_moments p1;             /* as returned by nqs_lanczos_moments */
+    double h4, h5, mu4, mu5;
+    double e_p2, beta1, beta2;
+    int32_t degenerate;
+} nqs_moments2;
 
 /* Statistics of one training step (nqs_vmc_step), all FP64. */
 typedef struct {
@@ -144,6 +162,22 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const int8_t* spins, int64_t S, double* logpsi
 nqs_status nqs_lanczos_moments(nqs_ctx* ctx, const int8_t* spins, int64_t S, int exact,
                                double* e1e2_out, nqs_moments* out, void* ws, size_t ws_bytes,
                                hipStream_t stream);
+
+/* e1, e2 and e3 = (H^3 psi)/psi per configuration, then the moments of
+ * nqs_moments2 and the p = 2 Lanczos energy (Sec. 3.3, Eq. (19) with p = 2).
+ * e3(s) = H_ss e2(s) + sum_b (J_b/2) psi(s^b)/psi(s) e2(s^b): the antiparallel
+ * neighbours s^b of each configuration (bond order) are written to the
+ * workspace and run through the same logpsi / E_loc / two-hop kernels as the
+ * configurations themselves, so the cost is about n_c times that of
+ * nqs_lanczos_moments.  exact as for nqs_lanczos_moments.  e123_out (complex
+ * [S][3]: e1, e2, e3) is optional.  Workspace:
+ * nqs_workspace_bytes(NQS_OP_MOMENTS2, S).  Synchronises the stream (once per
+ * chunk of configurations, to size the neighbour launches).  Returns
+ * NQS_WARN_DEGENERATE when the p = 2 step is degenerate (see nqs_moments2);
+ * NQS_ERR_NONFINITE when a moment is not finite. */
+nqs_status nqs_lanczos_moments_p2(nqs_ctx* ctx, const int8_t* spins, int64_t S, int exact,
+                                  double* e123_out, nqs_moments2* out, void* ws, size_t ws_bytes,
+                                  hipStream_t stream);
 
 /* Log-derivatives O_k = d log psi / d theta_k (Sec. 3.2, below Eq. (12)) for
  * every parameter in the nqs_set_params layout, summed over symmetry images:
@@ -264,7 +298,8 @@ nqs_status nqs_set_factor_form(nqs_ctx* ctx, int direct_only);
  * 5 twohop_finish, 6 moments, 7 grad, 8 sample, 9 sr (whole nqs_sr_solve),
  * 10 gram (the S x S Gram matrix of nqs_sr_solve), 11 cholesky (its blocked
  * factorisation and the two triangular solves), 12 sq (nqs_structure_factor),
- * 13 cg (nqs_sr_solve_cg)),
+ * 13 cg (nqs_sr_solve_cg), 14 hop3 (the neighbour expansion, e3 and
+ * fifth-order moment kernels of nqs_lanczos_moments_p2)),
  * the summed duration
  * in ms and the launch count since the last reset; reset = 1 clears them. */
 nqs_status nqs_profile_enable(nqs_ctx* ctx, int on);

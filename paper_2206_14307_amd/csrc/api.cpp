@@ -66,6 +66,8 @@ size_t chunk_bytes_per_sample(const nqs_ctx* c, int op) {
     case NQS_OP_LOGPSI: return z.L;
     case NQS_OP_ELOC: return z.L + z.w + z.t + z.partial;
     case NQS_OP_MOMENTS: return z.L + z.w + z.t + z.partial + z.partial2;
+    // plus the neighbour row, its log psi and e1, e2
+    case NQS_OP_MOMENTS2: return z.L + z.w + z.t + z.partial + z.partial2 + c->N + 48;
     case NQS_OP_GRAD: return z.L + z.w + z.t;
     default: return 0;
   }
@@ -75,6 +77,9 @@ int64_t chunk_of(const nqs_ctx* c, int op, int64_t S) {
   const size_t b = chunk_bytes_per_sample(c, op);
   if (b == 0 || S <= 0) return std::max<int64_t>(S, 1);
   const int64_t ch = (int64_t)std::max<size_t>(1, kChunkBytes / b);
+  // the p = 2 moments chunk counts neighbour configurations: at most NB per
+  // configuration, and at least one configuration's worth
+  if (op == NQS_OP_MOMENTS2) return std::max<int64_t>(std::min<int64_t>(ch, S * c->NB), c->NB);
   return std::min<int64_t>(ch, S);
 }
 
@@ -100,6 +105,13 @@ struct Work {
   double* logpsi = nullptr;
   double* result = nullptr;
   double* lp = nullptr;            // chunk log psi scratch when the caller wants none
+  double* e3 = nullptr;            // [S] complex (p = 2 moments)
+  int8_t* nb_spins = nullptr;      // [chunk][N] neighbour configurations
+  double* nb_lp = nullptr;         // [chunk] complex log psi of the neighbours
+  double* nb_e1e2 = nullptr;       // [chunk][2] complex e1, e2 of the neighbours
+  int32_t* nb_cnt = nullptr;       // [n_out] antiparallel bonds per configuration
+  int32_t* nb_off = nullptr;       // [n_out + 1] their exclusive scan
+  int64_t n_out = 0;               // configurations per neighbour chunk
   int64_t chunk = 1;
   size_t bytes = 0;
 };
@@ -108,11 +120,13 @@ Work plan(const nqs_ctx* c, int op, int64_t S, void* ws) {
   Work wk;
   Carve cv(ws);
   const ChunkSizes z = per_sample(c);
-  if (op == NQS_OP_MOMENTS) {
+  const bool mom = op == NQS_OP_MOMENTS || op == NQS_OP_MOMENTS2;
+  if (mom) {
     wk.e1e2 = (double*)cv.take((size_t)std::max<int64_t>(S, 1) * 32);
     wk.logpsi = (double*)cv.take((size_t)std::max<int64_t>(S, 1) * 16);
-    wk.result = (double*)cv.take(16 * 8);
+    wk.result = (double*)cv.take(32 * 8);
   }
+  if (op == NQS_OP_MOMENTS2) wk.e3 = (double*)cv.take((size_t)std::max<int64_t>(S, 1) * 16);
   const int64_t ch = chunk_of(c, op, S);
   wk.chunk = ch;
   if (fused_grad(c, op)) return wk;
@@ -127,9 +141,17 @@ Work plan(const nqs_ctx* c, int op, int64_t S, void* ws) {
     wk.w = cv.take(z.w * ch);
     wk.t = cv.take(z.t * ch);
   }
-  if (op == NQS_OP_ELOC || op == NQS_OP_MOMENTS) wk.partial = (double*)cv.take(z.partial * ch);
+  if (op == NQS_OP_ELOC || mom) wk.partial = (double*)cv.take(z.partial * ch);
   if (op == NQS_OP_ELOC || op == NQS_OP_GRAD) wk.lp = (double*)cv.take((size_t)16 * ch);
-  if (op == NQS_OP_MOMENTS) wk.partial2 = (double*)cv.take(z.partial2 * ch);
+  if (mom) wk.partial2 = (double*)cv.take(z.partial2 * ch);
+  if (op == NQS_OP_MOMENTS2) {
+    wk.n_out = std::max<int64_t>(1, ch / c->NB);
+    wk.nb_spins = (int8_t*)cv.take((size_t)ch * c->N);
+    wk.nb_lp = (double*)cv.take((size_t)ch * 16);
+    wk.nb_e1e2 = (double*)cv.take((size_t)ch * 32);
+    wk.nb_cnt = (int32_t*)cv.take((size_t)wk.n_out * 4);
+    wk.nb_off = (int32_t*)cv.take((size_t)(wk.n_out + 1) * 4);
+  }
   wk.bytes = cv.off;
   return wk;
 }
@@ -558,6 +580,104 @@ nqs_status nqs_lanczos_moments(nqs_ctx* c, const int8_t* spins, int64_t S, int e
   out->degenerate = r[12] != 0.0;
   for (int j = 0; j < 12; ++j)
     if (!std::isfinite(r[j])) return fail(c, NQS_ERR_NONFINITE, "non-finite moments");
+  return out->degenerate ? NQS_WARN_DEGENERATE : NQS_OK;
+}
+
+namespace {
+// e1 (E_loc) and e2 of n configurations into e1e2 [n][4], log psi into lp.
+hipError_t e1e2_chunk(nqs_ctx* c, const Work& wk, const int8_t* sp, int64_t n, double* lp,
+                      double* e1e2, hipStream_t st) {
+  hipError_t e = eloc_chunk(c, wk, sp, n, lp, e1e2, 4, st);
+  if (e == hipSuccess)
+    e = NQS_RUN(c, K_TWOHOP, st, launch_twohop(c, sp, n, wk.t, wk.w, wk.partial2, st));
+  if (e == hipSuccess)
+    e = NQS_RUN(c, K_TWOHOP_FIN, st, launch_twohop_finish(c, sp, n, wk.partial2, e1e2, st));
+  return e;
+}
+
+void fill_moments(nqs_moments* out, const double* r) {
+  out->n = (int64_t)r[13];
+  out->h1 = r[0];
+  out->h1_im = r[1];
+  out->h2 = r[2];
+  out->h2_alt = r[3];
+  out->h3 = r[4];
+  out->c2 = r[5];
+  out->c3 = r[6];
+  out->v = r[7];
+  out->r = r[8];
+  out->alpha = r[9];
+  out->e_p1 = r[10];
+  out->h1_err = r[11];
+  out->degenerate = r[12] != 0.0;
+}
+}  // namespace
+
+nqs_status nqs_lanczos_moments_p2(nqs_ctx* c, const int8_t* spins, int64_t S, int exact,
+                                  double* e123_out, nqs_moments2* out, void* ws, size_t ws_bytes,
+                                  hipStream_t st) {
+  nqs_status s = check_common(c, spins, S, ws, ws_bytes, NQS_OP_MOMENTS2);
+  if (s != NQS_OK) return s;
+  if (!out) return fail(c, NQS_ERR_ARG, "out is NULL");
+  if (S <= 0) return fail(c, NQS_ERR_ARG, "moments need S >= 1");
+  if (exact != 0 && exact != 1) return fail(c, NQS_ERR_ARG, "exact must be 0 or 1");
+  const Work wk = plan(c, NQS_OP_MOMENTS2, S, ws);
+  hipError_t e = hipSuccess;
+  // e1, e2 of the configurations
+  for (int64_t s0 = 0; s0 < S && e == hipSuccess; s0 += wk.chunk) {
+    const int64_t n = std::min(wk.chunk, S - s0);
+    e = e1e2_chunk(c, wk, spins + s0 * c->N, n, wk.logpsi + 2 * s0, wk.e1e2 + 4 * s0, st);
+  }
+  // e3 from the neighbours' log psi and e2, n_out configurations at a time
+  for (int64_t s0 = 0; s0 < S && e == hipSuccess; s0 += wk.n_out) {
+    const int64_t n = std::min(wk.n_out, S - s0);
+    const int8_t* sp = spins + s0 * c->N;
+    e = NQS_RUN(c, K_HOP3, st, launch_nb_count(c, sp, n, wk.nb_cnt, st));
+    if (e == hipSuccess) e = NQS_RUN(c, K_HOP3, st, launch_nb_scan(wk.nb_cnt, n, wk.nb_off, st));
+    int32_t total = 0;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&total, wk.nb_off + n, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) break;
+    if (total < 0 || total > wk.chunk)
+      return fail(c, NQS_ERR_DEVICE, "neighbour count " + std::to_string(total) +
+                                         " exceeds the chunk " + std::to_string(wk.chunk));
+    if (total > 0) {
+      e = NQS_RUN(c, K_HOP3, st, launch_nb_write(c, sp, n, wk.nb_off, wk.nb_spins, st));
+      if (e == hipSuccess) e = e1e2_chunk(c, wk, wk.nb_spins, total, wk.nb_lp, wk.nb_e1e2, st);
+    }
+    if (e == hipSuccess)
+      e = NQS_RUN(c, K_HOP3, st,
+                  launch_e3_combine(c, sp, n, wk.nb_off, wk.logpsi + 2 * s0, wk.e1e2 + 4 * s0,
+                                    wk.nb_lp, wk.nb_e1e2, wk.e3 + 2 * s0, st));
+  }
+  if (e == hipSuccess)
+    e = NQS_RUN(c, K_MOMENTS, st,
+                launch_moments(wk.e1e2, wk.logpsi, S, exact, nullptr, 0, wk.result, st));
+  if (e == hipSuccess)
+    e = NQS_RUN(c, K_HOP3, st, launch_moments2(wk.e1e2, wk.e3, wk.logpsi, S, exact, wk.result, st));
+  if (e == hipSuccess && e123_out) {
+    e = hipMemcpy2DAsync(e123_out, 48, wk.e1e2, 32, 32, (size_t)S, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync((char*)e123_out + 32, 48, wk.e3, 16, 16, (size_t)S,
+                           hipMemcpyDeviceToDevice, st);
+  }
+  double r[24];
+  if (e == hipSuccess) e = hipMemcpyAsync(r, wk.result, sizeof(r), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(c, e, "p = 2 moments");
+  fill_moments(&out->p1, r);
+  out->h4 = r[16];
+  out->h5 = r[17];
+  out->mu4 = r[18];
+  out->mu5 = r[19];
+  out->e_p2 = r[20];
+  out->beta1 = r[21];
+  out->beta2 = r[22];
+  out->degenerate = r[23] != 0.0;
+  for (int j = 0; j < 23; ++j)
+    if ((j < 12 || j >= 16) && !std::isfinite(r[j]))
+      return fail(c, NQS_ERR_NONFINITE, "non-finite moments");
   return out->degenerate ? NQS_WARN_DEGENERATE : NQS_OK;
 }
 

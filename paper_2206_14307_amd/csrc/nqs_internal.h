@@ -83,7 +83,7 @@ struct ParamTables {
 
 namespace nqs {
 enum KernelId { K_THETA = 0, K_LSE, K_ELOC, K_ELOC_FIN, K_TWOHOP, K_TWOHOP_FIN, K_MOMENTS,
-                K_GRAD, K_SAMPLE, K_SR, K_GRAM, K_CHOL, K_SQ, K_CG, K_COUNT };
+                K_GRAD, K_SAMPLE, K_SR, K_GRAM, K_CHOL, K_SQ, K_CG, K_HOP3, K_COUNT };
 struct Profiler {
   bool on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[K_COUNT];
@@ -184,6 +184,19 @@ hipError_t launch_params_step(const double* params, const double* dtheta, int64_
                               double* next, double* stats, hipStream_t st);
 hipError_t launch_sq(const nqs_ctx* c, const int8_t* spins, int64_t S, const double* weights,
                      double* out, void* ws, hipStream_t st);
+// Three-hop e3 (p = 2 Lanczos): per-configuration antiparallel-bond counts,
+// their exclusive scan (off[n] = total), the neighbour rows, e3 from the
+// neighbours' log psi and e2, and the fifth-order moments + 3x3 solve.
+hipError_t launch_nb_count(const nqs_ctx* c, const int8_t* spins, int64_t n, int32_t* cnt,
+                           hipStream_t st);
+hipError_t launch_nb_scan(const int32_t* cnt, int64_t n, int32_t* off, hipStream_t st);
+hipError_t launch_nb_write(const nqs_ctx* c, const int8_t* spins, int64_t n, const int32_t* off,
+                           int8_t* out, hipStream_t st);
+hipError_t launch_e3_combine(const nqs_ctx* c, const int8_t* spins, int64_t n, const int32_t* off,
+                             const double* lp, const double* e1e2, const double* lp_nb,
+                             const double* e1e2_nb, double* e3, hipStream_t st);
+hipError_t launch_moments2(const double* e1e2, const double* e3, const double* logpsi, int64_t S,
+                           int exact, double* result, hipStream_t st);
 hipError_t launch_grad(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
                        const void* w, void* O_out, hipStream_t st);
 

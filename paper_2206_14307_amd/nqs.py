@@ -19,16 +19,17 @@ NQS_OK, NQS_ERR_ARG, NQS_ERR_DEVICE, NQS_ERR_OOM, NQS_ERR_NONFINITE, NQS_WARN_DE
     NQS_ERR_NOT_PD = range(7)
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 IRREP = {"A1": 0, "A2": 1, "B1": 2, "B2": 3}
-OP = {"logpsi": 0, "eloc": 1, "moments": 2, "grad": 3, "sr": 4, "sample": 5, "sq": 6, "vmc": 7, "cg": 8}
+OP = {"logpsi": 0, "eloc": 1, "moments": 2, "grad": 3, "sr": 4, "sample": 5, "sq": 6, "vmc": 7, "cg": 8,
+      "moments2": 9}
 
 EXPORTS = ["nqs_create", "nqs_destroy", "nqs_num_params", "nqs_workspace_bytes", "nqs_set_params",
-           "nqs_logpsi", "nqs_eloc", "nqs_lanczos_moments", "nqs_grad", "nqs_sr_solve",
+           "nqs_logpsi", "nqs_eloc", "nqs_lanczos_moments", "nqs_lanczos_moments_p2", "nqs_grad", "nqs_sr_solve",
            "nqs_chain_init", "nqs_sample", "nqs_enumerate_sz0", "nqs_set_factor_form",
            "nqs_structure_factor", "nqs_get_params", "nqs_vmc_step", "nqs_sr_solve_cg",
            "nqs_profile_enable", "nqs_profile_read", "nqs_status_str", "nqs_last_error"]
 KERNELS = {"theta": 0, "lse": 1, "eloc_bonds": 2, "eloc_finish": 3, "twohop": 4,
            "twohop_finish": 5, "moments": 6, "grad": 7, "sample": 8, "sr": 9, "gram": 10,
-           "cholesky": 11, "sq": 12, "cg": 13}
+           "cholesky": 11, "sq": 12, "cg": 13, "hop3": 14}
 
 
 class ModelDesc(C.Structure):
@@ -41,6 +42,11 @@ class Moments(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, C.c_double) for k in (
         "h1", "h1_im", "h2", "h2_alt", "h3", "c2", "c3", "v", "r", "alpha", "e_p1", "h1_err")] + [
         ("degenerate", C.c_int32)]
+
+
+class Moments2(C.Structure):
+    _fields_ = [("p1", Moments)] + [(k, C.c_double) for k in (
+        "h4", "h5", "mu4", "mu5", "e_p2", "beta1", "beta2")] + [("degenerate", C.c_int32)]
 
 
 class VmcStats(C.Structure):
@@ -77,6 +83,8 @@ def load_library(path: str = LIB_PATH):
         "nqs_eloc": ([vp, vp, i64, vp, vp, vp, C.c_size_t, vp], C.c_int),
         "nqs_lanczos_moments": ([vp, vp, i64, C.c_int, vp, C.POINTER(Moments), vp, C.c_size_t, vp],
                                 C.c_int),
+        "nqs_lanczos_moments_p2": ([vp, vp, i64, C.c_int, vp, C.POINTER(Moments2), vp, C.c_size_t,
+                                    vp], C.c_int),
         "nqs_grad": ([vp, vp, i64, vp, vp, vp, C.c_size_t, vp], C.c_int),
         "nqs_sr_solve": ([vp, vp, vp, i64, dbl, dbl, vp, vp, C.c_size_t, vp], C.c_int),
         "nqs_chain_init": ([vp, vp, i64, u64, vp, vp], C.c_int),
@@ -272,6 +280,27 @@ class NQS:
         res["degenerate"] = bool(res["degenerate"])
         res["status"] = st
         return res, e12
+
+    def lanczos_moments_p2(self, spins, exact=False, want_e123=True):
+        """Moments to fifth order and the p = 2 Lanczos energy; returns
+        (dict, e123) with e123 complex128 [S][3] = (e1, e2, e3) or None.  The
+        dict holds the p = 1 fields and h4 h5 mu4 mu5 e_p2 beta1 beta2;
+        degenerate / degenerate1 are the p = 2 / p = 1 flags."""
+        sp = self._spins(spins)
+        S = sp.shape[0]
+        e123 = torch.empty((S, 3), dtype=torch.complex128, device=self.device) if want_e123 else None
+        ws = self.workspace("moments2", S)
+        m = Moments2()
+        st = self._check(self.lib.nqs_lanczos_moments_p2(self._ctx, _ptr(sp), S, int(bool(exact)),
+                                                         _ptr(e123), C.byref(m), _ptr(ws),
+                                                         ws.numel(), _stream()),
+                         "nqs_lanczos_moments_p2")
+        res = {k: getattr(m.p1, k) for k, _ in Moments._fields_}
+        res["degenerate1"] = bool(res.pop("degenerate"))
+        res.update({k: getattr(m, k) for k, _ in Moments2._fields_[1:]})
+        res["degenerate"] = bool(res["degenerate"])
+        res["status"] = st
+        return res, e123
 
     def grad(self, spins, want_logpsi=False):
         sp = self._spins(spins)
