@@ -218,8 +218,14 @@ def timed(fn, steps, warmup):
 
 
 def twohop_hops(spins, bonds):
-    """Exchange factors per image and hidden unit of e1 + e2 over a set of
-    configurations: one-hop n_c(s) plus two-hop sum_{b1} n_c(s^{b1})."""
+    """Exchange-factor products (per image and hidden unit) that e1 + e2 of a
+    set of configurations evaluate: the n_c(s) first hops, and for each first
+    hop b1 the second hops b2 antiparallel in s^{b1}, b2 != b1 (the exchange
+    back is closed-form), bonds disjoint from b1 once per unordered pair."""
+    NB = len(bonds)
+    idx = np.arange(NB)
+    shared = ((bonds[:, None, 0] == bonds[None, :, 0]) | (bonds[:, None, 0] == bonds[None, :, 1]) |
+              (bonds[:, None, 1] == bonds[None, :, 0]) | (bonds[:, None, 1] == bonds[None, :, 1]))
     hops = 0
     for s0 in range(0, len(spins), 512):
         x = spins[s0:s0 + 512].astype(np.int16)
@@ -230,7 +236,8 @@ def twohop_hops(spins, bonds):
             if rows.size:
                 y = x[rows].copy()
                 y[:, [i, j]] = -y[:, [i, j]]
-                hops += int((y[:, bonds[:, 0]] != y[:, bonds[:, 1]]).sum())
+                keep = (idx != b) & (shared[b] | (idx > b))
+                hops += int(((y[:, bonds[:, 0]] != y[:, bonds[:, 1]]) & keep).sum())
     return hops
 
 

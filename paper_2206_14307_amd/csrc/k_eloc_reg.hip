@@ -50,6 +50,35 @@ __device__ __forceinline__ int build_list(const int8_t* srow, const int32_t* bon
   return n;
 }
 
+// Second-hop list of the two-hop kernel for first hop b1 = (i1, j1): the
+// antiparallel bonds b2 of s^{b1} except b1 itself (exchanging it back returns
+// s, a term added in closed form), and of the bonds that share no site with
+// b1 only those with b2 > b1: their exchange commutes with b1's, so the
+// configuration s^{b1 b2} = s^{b2 b1} and its weight (J1 J2 / 4) are the same
+// for both orders, and the entry (flag 0x4000) counts twice.
+__device__ __forceinline__ int build_list_pairs(const int8_t* row2, const int32_t* bonds, int NB,
+                                                int16_t* list, int lane, int b1, int i1, int j1) {
+  int n = 0;
+  for (int base = 0; base < NB; base += 64) {
+    const int b = base + lane;
+    bool keep = false, twice = false;
+    if (b < NB && b != b1) {
+      const int i = bonds[2 * b], j = bonds[2 * b + 1];
+      if (row2[i] != row2[j]) {
+        const bool shared = i == i1 || i == j1 || j == i1 || j == j1;
+        keep = shared || b > b1;
+        twice = !shared;
+      }
+    }
+    const unsigned long long m = __ballot(keep);
+    const int pos = __popcll(m & ((1ull << lane) - 1ull));
+    if (keep) list[n + pos] = (int16_t)(b | (twice ? 0x4000 : 0));
+    n += __popcll(m);
+  }
+  wave_sync_lds();
+  return n;
+}
+
 // P <- P * (s + t T)
 template <typename R>
 __device__ __forceinline__ void mul_s_plus(R& pr, R& pi, R s, R tr, R ti, R Tr, R Ti) {
@@ -268,7 +297,7 @@ __global__ __launch_bounds__(64 * kRegWaves) void twohop_reg_kernel(
       row2[j1] = srow[i1];
     }
     wave_sync_lds();
-    const int nc2 = build_list(row2, bonds, NB, l2, lane);
+    const int nc2 = build_list_pairs(row2, bonds, NB, l2, lane, b1, i1, j1);
     double diag2 = 0.0;
     for (int b = lane; b < NB; b += 64)
       diag2 += 0.25 * bond_J[b] * (double)(row2[bonds[2 * b]] * row2[bonds[2 * b + 1]]);
@@ -361,15 +390,22 @@ __global__ __launch_bounds__(64 * kRegWaves) void twohop_reg_kernel(
       if (half == 0) {
         accr += diag2 * (double)(g1r * pr - g1i * pi);
         acci += diag2 * (double)(g1r * pi + g1i * pr);
+        // b1 exchanged back: s^{b1 b1} = s, ratio 1 in every image
+        const double jj = 0.25 * bond_J[b1] * bond_J[b1];
+        accr += jj * (double)wr;
+        acci += jj * (double)wi;
       }
     }
     for (int i0 = 0; i0 < nc2; i0 += 2) {
       int beta[2], sidx[2];
       R sgn[2];
+      double mult[2];
 #pragma unroll
       for (int n = 0; n < 2; ++n) {
         const int ii = i0 + n;
-        const int b = l2[ii < nc2 ? ii : i0];
+        const int e = l2[ii < nc2 ? ii : i0];
+        const int b = e & 0x3fff;
+        mult[n] = (e & 0x4000) ? 2.0 : 1.0;
         const int v = bmap[(size_t)g * NB + b];
         beta[n] = v >> 1;
         const int s_b = -(int)row2[bonds[2 * b]];
@@ -439,8 +475,8 @@ __global__ __launch_bounds__(64 * kRegWaves) void twohop_reg_kernel(
       const bool valid = i0 + half < nc2;
       const R* f2 = F + ((size_t)beta[half] * 2 + sidx[half]) * 2;
       const R hr = f2[0] * g1r - f2[1] * g1i, hi = f2[0] * g1i + f2[1] * g1r;
-      accr += valid ? (double)(hr * pr - hi * pi) : 0.0;
-      acci += valid ? (double)(hr * pi + hi * pr) : 0.0;
+      accr += valid ? mult[half] * (double)(hr * pr - hi * pi) : 0.0;
+      acci += valid ? mult[half] * (double)(hr * pi + hi * pr) : 0.0;
     }
     accr = wave_sum(accr);
     acci = wave_sum(acci);
