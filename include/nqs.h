@@ -154,7 +154,11 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const int8_t* spins, int64_t S, double* logpsi
 
 /* e1 = E_loc and e2 = (H^2 psi)/psi per configuration (two-hop connected
  * configurations), then the FP64 moments and p = 1 Lanczos energy
- * (Sec. 3.3).  exact = 0: uniform weights (Monte-Carlo samples);
+ * (Sec. 3.3).  For models without the register-resident two-hop kernel
+ * (K > 1, or K*M beyond its compiled sizes) e2 is formed as
+ * H_ss e1 + sum_b (J_b/2) psi(s^b)/psi(s) E_loc(s^b) from the fused / wide
+ * E_loc kernels run on the exchange neighbours, which synchronises once per
+ * chunk of configurations.  exact = 0: uniform weights (Monte-Carlo samples);
  * exact = 1: Born weights |psi|^2 / sum |psi|^2 (Sec. 3.2, Eq. (9)) over the
  * given configurations (the whole Sz = 0 sector for exact results).
  * e1e2_out (complex [S][2]) is optional.  Writes *out and synchronises the
@@ -298,8 +302,9 @@ nqs_status nqs_set_factor_form(nqs_ctx* ctx, int direct_only);
  * 5 twohop_finish, 6 moments, 7 grad, 8 sample, 9 sr (whole nqs_sr_solve),
  * 10 gram (the S x S Gram matrix of nqs_sr_solve), 11 cholesky (its blocked
  * factorisation and the two triangular solves), 12 sq (nqs_structure_factor),
- * 13 cg (nqs_sr_solve_cg), 14 hop3 (the neighbour expansion, e3 and
- * fifth-order moment kernels of nqs_lanczos_moments_p2)),
+ * 13 cg (nqs_sr_solve_cg), 14 hop3 (the neighbour expansion and combine
+ * kernels of nqs_lanczos_moments and nqs_lanczos_moments_p2, and the
+ * fifth-order moment kernel)),
  * the summed duration
  * in ms and the launch count since the last reset; reset = 1 clears them. */
 nqs_status nqs_profile_enable(nqs_ctx* ctx, int on);

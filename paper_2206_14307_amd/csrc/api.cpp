@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "nqs_internal.h"
+#include "hops.h"
 
 using namespace nqs;
 
@@ -56,6 +57,12 @@ bool fused_eloc(const nqs_ctx* c, int op) {
   return op == NQS_OP_ELOC && (eloc_fused_supported(c) || eloc_wide_supported(c));
 }
 bool fused_grad(const nqs_ctx* c, int op) { return op == NQS_OP_GRAD && grad_fused_supported(c); }
+// nqs_lanczos_moments forms e2 from the exchange neighbours' E_loc (fused or
+// wide kernel) when no register-resident two-hop kernel covers the model
+bool composed_moments(const nqs_ctx* c, int op) {
+  return op == NQS_OP_MOMENTS && !twohop_reg_supported(c) &&
+         (eloc_fused_supported(c) || eloc_wide_supported(c));
+}
 size_t fused_part_bytes(const nqs_ctx* c) { return (size_t)(c->G / 16) * 6 * 8; }
 
 size_t chunk_bytes_per_sample(const nqs_ctx* c, int op) {
@@ -127,6 +134,22 @@ Work plan(const nqs_ctx* c, int op, int64_t S, void* ws) {
     wk.result = (double*)cv.take(32 * 8);
   }
   if (op == NQS_OP_MOMENTS2) wk.e3 = (double*)cv.take((size_t)std::max<int64_t>(S, 1) * 16);
+  if (composed_moments(c, op)) {
+    // chunk = neighbour configurations per E_loc launch (at most NB per configuration)
+    const size_t b = fused_part_bytes(c) + c->N + 48;
+    int64_t ch = (int64_t)std::max<size_t>(1, kChunkBytes / b);
+    ch = std::max<int64_t>(std::min<int64_t>(ch, std::max<int64_t>(S, 1) * c->NB), c->NB);
+    wk.chunk = ch;
+    wk.n_out = std::max<int64_t>(1, ch / c->NB);
+    wk.partial = (double*)cv.take(fused_part_bytes(c) * ch);
+    wk.nb_spins = (int8_t*)cv.take((size_t)ch * c->N);
+    wk.nb_lp = (double*)cv.take((size_t)ch * 16);
+    wk.nb_e1e2 = (double*)cv.take((size_t)ch * 32);
+    wk.nb_cnt = (int32_t*)cv.take((size_t)wk.n_out * 4);
+    wk.nb_off = (int32_t*)cv.take((size_t)(wk.n_out + 1) * 4);
+    wk.bytes = cv.off;
+    return wk;
+  }
   const int64_t ch = chunk_of(c, op, S);
   wk.chunk = ch;
   if (fused_grad(c, op)) return wk;
@@ -493,6 +516,33 @@ nqs_status nqs_logpsi(nqs_ctx* c, const int8_t* spins, int64_t S, double* logpsi
 }
 
 namespace {
+// log psi and E_loc of n configurations with the fused (K*M <= 128) or wide
+// kernel; part holds the per-(configuration, 16-image block) partials.
+hipError_t eloc_fused_any(nqs_ctx* c, const int8_t* sp, int64_t n, double* part, double* lp,
+                          double* eloc, int eloc_stride, hipStream_t st) {
+  if (eloc_fused_supported(c))
+    return NQS_RUN(c, K_ELOC, st, launch_eloc_fused(c, sp, n, part, lp, eloc, eloc_stride, st));
+  hipError_t e = NQS_RUN(c, K_ELOC, st, launch_eloc_wide(c, sp, n, part, st));
+  if (e == hipSuccess)
+    e = NQS_RUN(c, K_ELOC_FIN, st, launch_fused_finish(c, sp, n, part, lp, eloc, eloc_stride, st));
+  return e;
+}
+
+// Neighbour rows of n configurations into wk.nb_spins (bond order; wk.nb_off
+// their offsets); *total = their number (reads it back: synchronises).
+hipError_t expand_neighbours(nqs_ctx* c, const Work& wk, const int8_t* sp, int64_t n,
+                             int32_t* total, hipStream_t st) {
+  *total = 0;
+  hipError_t e = NQS_RUN(c, K_HOP3, st, launch_nb_count(c, sp, n, wk.nb_cnt, st));
+  if (e == hipSuccess) e = NQS_RUN(c, K_HOP3, st, launch_nb_scan(wk.nb_cnt, n, wk.nb_off, st));
+  if (e == hipSuccess) e = hipMemcpyAsync(total, wk.nb_off + n, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  if (*total < 0 || *total > wk.chunk) return hipErrorInvalidValue;
+  if (*total > 0) e = NQS_RUN(c, K_HOP3, st, launch_nb_write(c, sp, n, wk.nb_off, wk.nb_spins, st));
+  return e;
+}
+
 // theta (+t) -> LSE (+w) -> bond sums -> E_loc, one chunk.
 hipError_t eloc_chunk(nqs_ctx* c, const Work& wk, const int8_t* sp, int64_t n, double* logpsi,
                       double* eloc, int eloc_stride, hipStream_t st) {
@@ -545,7 +595,28 @@ nqs_status nqs_lanczos_moments(nqs_ctx* c, const int8_t* spins, int64_t S, int e
   if (exact != 0 && exact != 1) return fail(c, NQS_ERR_ARG, "exact must be 0 or 1");
   const Work wk = plan(c, NQS_OP_MOMENTS, S, ws);
   hipError_t e = hipSuccess;
-  for (int64_t s0 = 0; s0 < S && e == hipSuccess; s0 += wk.chunk) {
+  // e2 = H_ss e1 + sum_b (J_b/2) psi(s^b)/psi(s) E_loc(s^b) from the fused / wide kernels
+  for (int64_t s0 = 0; composed_moments(c, NQS_OP_MOMENTS) && s0 < S && e == hipSuccess;
+       s0 += wk.n_out) {
+    const int64_t n = std::min(wk.n_out, S - s0);
+    const int8_t* sp = spins + s0 * c->N;
+    double* lp = wk.logpsi + 2 * s0;
+    double* e12 = wk.e1e2 + 4 * s0;
+    e = eloc_fused_any(c, sp, n, wk.partial, lp, e12, 4, st);
+    int32_t total = 0;
+    if (e == hipSuccess) e = expand_neighbours(c, wk, sp, n, &total, st);
+    if (e == hipErrorInvalidValue)
+      return fail(c, NQS_ERR_DEVICE, "neighbour count " + std::to_string(total) +
+                                         " exceeds the chunk " + std::to_string(wk.chunk));
+    if (e == hipSuccess && total > 0)
+      e = eloc_fused_any(c, wk.nb_spins, total, wk.partial, wk.nb_lp, wk.nb_e1e2, 4, st);
+    if (e == hipSuccess)
+      e = NQS_RUN(c, K_HOP3, st,
+                  launch_hop_combine(c, sp, n, wk.nb_off, lp, e12, 4, wk.nb_lp, wk.nb_e1e2, 4,
+                                     e12 + 2, 4, st));
+  }
+  for (int64_t s0 = 0; !composed_moments(c, NQS_OP_MOMENTS) && s0 < S && e == hipSuccess;
+       s0 += wk.chunk) {
     const int64_t n = std::min(wk.chunk, S - s0);
     const int8_t* sp = spins + s0 * c->N;
     e = eloc_chunk(c, wk, sp, n, wk.logpsi + 2 * s0, wk.e1e2 + 4 * s0, 4, st);
@@ -632,20 +703,13 @@ nqs_status nqs_lanczos_moments_p2(nqs_ctx* c, const int8_t* spins, int64_t S, in
   for (int64_t s0 = 0; s0 < S && e == hipSuccess; s0 += wk.n_out) {
     const int64_t n = std::min(wk.n_out, S - s0);
     const int8_t* sp = spins + s0 * c->N;
-    e = NQS_RUN(c, K_HOP3, st, launch_nb_count(c, sp, n, wk.nb_cnt, st));
-    if (e == hipSuccess) e = NQS_RUN(c, K_HOP3, st, launch_nb_scan(wk.nb_cnt, n, wk.nb_off, st));
     int32_t total = 0;
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(&total, wk.nb_off + n, 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) break;
-    if (total < 0 || total > wk.chunk)
+    e = expand_neighbours(c, wk, sp, n, &total, st);
+    if (e == hipErrorInvalidValue)
       return fail(c, NQS_ERR_DEVICE, "neighbour count " + std::to_string(total) +
                                          " exceeds the chunk " + std::to_string(wk.chunk));
-    if (total > 0) {
-      e = NQS_RUN(c, K_HOP3, st, launch_nb_write(c, sp, n, wk.nb_off, wk.nb_spins, st));
-      if (e == hipSuccess) e = e1e2_chunk(c, wk, wk.nb_spins, total, wk.nb_lp, wk.nb_e1e2, st);
-    }
+    if (e == hipSuccess && total > 0)
+      e = e1e2_chunk(c, wk, wk.nb_spins, total, wk.nb_lp, wk.nb_e1e2, st);
     if (e == hipSuccess)
       e = NQS_RUN(c, K_HOP3, st,
                   launch_e3_combine(c, sp, n, wk.nb_off, wk.logpsi + 2 * s0, wk.e1e2 + 4 * s0,

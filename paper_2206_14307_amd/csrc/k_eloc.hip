@@ -25,6 +25,7 @@
 // T rows.  Reductions are deterministic (fixed order, no float atomics).
 #include "device_common.h"
 #include "nqs_internal.h"
+#include "pair_list.h"
 
 namespace nqs {
 
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(256) void twohop_kernel(
     row2[j1] = srow[i1];
   }
   wave_sync_lds();
-  const int nc2 = build_anti_list(row2, bonds, NB, l2, lane);
+  const int nc2 = build_pair_list(row2, bonds, NB, l2, lane, b1, i1, j1);
   const double diag2 = diag_of(row2, bonds, bond_J, NB, lane);
   wave_sync_lds();
 
@@ -228,6 +229,10 @@ __global__ __launch_bounds__(256) void twohop_kernel(
     if (half == 0) {
       accr += diag2 * (double)(wr * pr - wi * pi);
       acci += diag2 * (double)(wr * pi + wi * pr);
+      // b1 exchanged back: s^{b1 b1} = s, ratio 1 in every image
+      const double jj = 0.25 * bond_J[b1] * bond_J[b1];
+      accr += jj * (double)wr;
+      acci += jj * (double)wi;
     }
   }
   // second hop
@@ -238,8 +243,9 @@ __global__ __launch_bounds__(256) void twohop_kernel(
 #pragma unroll
     for (int n = 0; n < NBD; ++n) {
       const int ii = i0 + 2 * n;
-      valid[n] = ii < nc2 ? R(1) : R(0);
-      const int b = ii < nc2 ? l2[ii] : l2[0];
+      const int e = ii < nc2 ? l2[ii] : l2[0];
+      valid[n] = ii < nc2 ? ((e & kPairTwice) ? R(2) : R(1)) : R(0);
+      const int b = e & kPairBond;
       const int v = bmap[(size_t)g * NB + b];
       const int beta = v >> 1;
       const int s_b = -(int)row2[bonds[2 * b]];

@@ -14,6 +14,8 @@
 // four independent FMA chains per lane.
 #include "device_common.h"
 #include "nqs_internal.h"
+#include "pair_list.h"
+#include "hops.h"
 
 namespace nqs {
 
@@ -44,35 +46,6 @@ __device__ __forceinline__ int build_list(const int8_t* srow, const int32_t* bon
     const unsigned long long m = __ballot(anti);
     const int pos = __popcll(m & ((1ull << lane) - 1ull));
     if (anti) list[n + pos] = (int16_t)b;
-    n += __popcll(m);
-  }
-  wave_sync_lds();
-  return n;
-}
-
-// Second-hop list of the two-hop kernel for first hop b1 = (i1, j1): the
-// antiparallel bonds b2 of s^{b1} except b1 itself (exchanging it back returns
-// s, a term added in closed form), and of the bonds that share no site with
-// b1 only those with b2 > b1: their exchange commutes with b1's, so the
-// configuration s^{b1 b2} = s^{b2 b1} and its weight (J1 J2 / 4) are the same
-// for both orders, and the entry (flag 0x4000) counts twice.
-__device__ __forceinline__ int build_list_pairs(const int8_t* row2, const int32_t* bonds, int NB,
-                                                int16_t* list, int lane, int b1, int i1, int j1) {
-  int n = 0;
-  for (int base = 0; base < NB; base += 64) {
-    const int b = base + lane;
-    bool keep = false, twice = false;
-    if (b < NB && b != b1) {
-      const int i = bonds[2 * b], j = bonds[2 * b + 1];
-      if (row2[i] != row2[j]) {
-        const bool shared = i == i1 || i == j1 || j == i1 || j == j1;
-        keep = shared || b > b1;
-        twice = !shared;
-      }
-    }
-    const unsigned long long m = __ballot(keep);
-    const int pos = __popcll(m & ((1ull << lane) - 1ull));
-    if (keep) list[n + pos] = (int16_t)(b | (twice ? 0x4000 : 0));
     n += __popcll(m);
   }
   wave_sync_lds();
@@ -297,7 +270,7 @@ __global__ __launch_bounds__(64 * kRegWaves) void twohop_reg_kernel(
       row2[j1] = srow[i1];
     }
     wave_sync_lds();
-    const int nc2 = build_list_pairs(row2, bonds, NB, l2, lane, b1, i1, j1);
+    const int nc2 = build_pair_list(row2, bonds, NB, l2, lane, b1, i1, j1);
     double diag2 = 0.0;
     for (int b = lane; b < NB; b += 64)
       diag2 += 0.25 * bond_J[b] * (double)(row2[bonds[2 * b]] * row2[bonds[2 * b + 1]]);
@@ -404,8 +377,8 @@ __global__ __launch_bounds__(64 * kRegWaves) void twohop_reg_kernel(
       for (int n = 0; n < 2; ++n) {
         const int ii = i0 + n;
         const int e = l2[ii < nc2 ? ii : i0];
-        const int b = e & 0x3fff;
-        mult[n] = (e & 0x4000) ? 2.0 : 1.0;
+        const int b = e & kPairBond;
+        mult[n] = (e & kPairTwice) ? 2.0 : 1.0;
         const int v = bmap[(size_t)g * NB + b];
         beta[n] = v >> 1;
         const int s_b = -(int)row2[bonds[2 * b]];
@@ -518,9 +491,15 @@ hipError_t launch_eloc_bonds_reg(const nqs_ctx* c, const int8_t* spins, int64_t 
   return hipErrorNotSupported;
 }
 
+bool twohop_reg_supported(const nqs_ctx* c) {
+  if (c->K != 1) return false;
+  if (c->prec == NQS_FP64) return c->N == 16 && c->M == 16;
+  return (c->N == 16 && c->M == 16) || (c->N == 36 && c->M == 72);
+}
+
 hipError_t launch_twohop_reg(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
                              const void* w, double* partial2, hipStream_t st) {
-  if (c->K != 1) return hipErrorNotSupported;
+  if (!twohop_reg_supported(c)) return hipErrorNotSupported;
   if (c->prec == NQS_FP64) {
     if (c->N == 16 && c->M == 16) return run_twohop<double, 16, 16>(c, spins, S, t, w, partial2, st);
   } else {

@@ -5,11 +5,14 @@
 // over the bonds b whose spins are antiparallel in s.  The neighbours s^b
 // are written out as ordinary configurations (compacted, bond order per
 // configuration) so that the library's logpsi / E_loc / two-hop kernels give
-// log psi(s^b) and e2(s^b); the combine kernel then forms e3.  The moments
+// log psi(s^b) and e2(s^b); the combine kernel then forms e3.  The same
+// combine forms e2 from the neighbours' E_loc for models without the
+// register-resident two-hop kernel.  The moments
 // kernel adds <|e2|^2>, Re<conj(e2) e3> and the centred mu4, mu5 to the p = 1
 // results, and one thread solves the 3x3 Krylov eigenproblem.
 #include "device_common.h"
 #include "nqs_internal.h"
+#include "hops.h"
 
 namespace nqs {
 
@@ -87,13 +90,14 @@ __global__ __launch_bounds__(64 * kNbWaves) void nb_write_kernel(const int8_t* _
   }
 }
 
-// e3[s] = H_ss e2[s] + sum_k (J_k/2) exp(lp_nb[k] - lp[s]) e2_nb[k]; the lanes
+// out[s] = H_ss eprev[s] + sum_k (J_k/2) exp(lp_nb[k] - lp[s]) enb[k]; the lanes
 // take the bonds, the wavefront sum runs in a fixed order.
-__global__ __launch_bounds__(64 * kNbWaves) void e3_combine_kernel(
+__global__ __launch_bounds__(64 * kNbWaves) void hop_combine_kernel(
     const int8_t* __restrict__ spins, int64_t n, int N, int NB, const int32_t* __restrict__ bonds,
     const double* __restrict__ bond_J, const int32_t* __restrict__ off,
-    const double* __restrict__ lp, const double* __restrict__ e1e2,
-    const double* __restrict__ lp_nb, const double* __restrict__ e1e2_nb, double* __restrict__ e3) {
+    const double* __restrict__ lp, const double* __restrict__ eprev, int eprev_stride,
+    const double* __restrict__ lp_nb, const double* __restrict__ enb, int enb_stride,
+    double* __restrict__ out, int out_stride) {
   const int64_t s = (int64_t)blockIdx.x * kNbWaves + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (s >= n) return;
@@ -113,11 +117,16 @@ __global__ __launch_bounds__(64 * kNbWaves) void e3_combine_kernel(
     if (anti) {
       const int64_t k = pos + __popcll(m & ((1ull << lane) - 1ull));
       const double mag = 0.5 * bond_J[b] * exp(lp_nb[2 * k] - lr);
-      double sn, cs;
-      sincos(lp_nb[2 * k + 1] - li, &sn, &cs);
-      const double fr = e1e2_nb[4 * k + 2], fi = e1e2_nb[4 * k + 3];
-      ar += mag * (cs * fr - sn * fi);
-      ai += mag * (cs * fi + sn * fr);
+      // psi(s^b) = 0 (a configuration fixed by a symmetry whose character
+      // forces a zero): the local value there is undefined, but H^p psi
+      // lies in the same symmetry sector and vanishes there too
+      if (mag != 0.0) {
+        double sn, cs;
+        sincos(lp_nb[2 * k + 1] - li, &sn, &cs);
+        const double fr = enb[enb_stride * k], fi = enb[enb_stride * k + 1];
+        ar += mag * (cs * fr - sn * fi);
+        ai += mag * (cs * fi + sn * fr);
+      }
     }
     pos += __popcll(m);
   }
@@ -125,8 +134,8 @@ __global__ __launch_bounds__(64 * kNbWaves) void e3_combine_kernel(
   ar = wave_sum(ar);
   ai = wave_sum(ai);
   if (lane == 0) {
-    e3[2 * s] = diag * e1e2[4 * s + 2] + ar;
-    e3[2 * s + 1] = diag * e1e2[4 * s + 3] + ai;
+    out[out_stride * s] = diag * eprev[eprev_stride * s] + ar;
+    out[out_stride * s + 1] = diag * eprev[eprev_stride * s + 1] + ai;
   }
 }
 
@@ -291,14 +300,21 @@ hipError_t launch_nb_write(const nqs_ctx* c, const int8_t* spins, int64_t n, con
   return hipGetLastError();
 }
 
+hipError_t launch_hop_combine(const nqs_ctx* c, const int8_t* spins, int64_t n, const int32_t* off,
+                              const double* lp, const double* eprev, int eprev_stride,
+                              const double* lp_nb, const double* enb, int enb_stride, double* out,
+                              int out_stride, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hop_combine_kernel<<<nb_blocks(n), 64 * kNbWaves, 0, st>>>(
+      spins, n, c->N, c->NB, c->dev.bonds, c->dev.bond_J, off, lp, eprev, eprev_stride, lp_nb, enb,
+      enb_stride, out, out_stride);
+  return hipGetLastError();
+}
+
 hipError_t launch_e3_combine(const nqs_ctx* c, const int8_t* spins, int64_t n, const int32_t* off,
                              const double* lp, const double* e1e2, const double* lp_nb,
                              const double* e1e2_nb, double* e3, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  e3_combine_kernel<<<nb_blocks(n), 64 * kNbWaves, 0, st>>>(spins, n, c->N, c->NB, c->dev.bonds,
-                                                            c->dev.bond_J, off, lp, e1e2, lp_nb,
-                                                            e1e2_nb, e3);
-  return hipGetLastError();
+  return launch_hop_combine(c, spins, n, off, lp, e1e2 + 2, 4, lp_nb, e1e2_nb + 2, 4, e3, 2, st);
 }
 
 hipError_t launch_moments2(const double* e1e2, const double* e3, const double* logpsi, int64_t S,

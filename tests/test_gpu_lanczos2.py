@@ -176,3 +176,45 @@ def test_p2_eigenstate_is_degenerate():
     assert res["degenerate"] and res["degenerate1"]
     assert res["e_p2"] == res["e_p1"] == res["h1"]
     assert abs(res["h1"] - 12.0) < 1e-12 and res["beta2"] == 0.0
+
+
+# ------------------------------------------- models without the register two-hop
+
+@pytest.mark.parametrize("irrep", ["A1", "B1"])
+def test_composed_e2_and_p2_k2_fp64_exact(sector16, irrep):
+    """K = 2 RBMs (no register-resident two-hop kernel): p = 1 forms e2 from the
+    neighbours' E_loc (fused kernel), p = 2 runs the generic two-hop kernel on
+    the neighbours; both against H^k psi / psi over the whole sector."""
+    w = dataclasses.replace(WORKLOADS["4x4_fp64_exact"], n_rbm=2, n_hidden=8, is_complex=True,
+                            irrep=irrep)
+    p = stress_params(w, 0.1, 8)
+    om = oracle.Model.from_workload(w)
+    masks, spins = sector16
+    psi, H, e1, e2, e3 = krylov_locals(om, p, masks, spins)
+    keep = np.abs(psi) > 1e-6 * np.abs(psi).max()          # B1 has symmetry zeros
+    m = make(w, p)
+    res1, e12 = m.lanczos_moments(cuda(spins[keep]), exact=True)
+    e12 = e12.cpu().numpy()
+    assert max_rel_err(e12[:, 0], e1[keep]) < TOL["fp64"]
+    assert max_rel_err(e12[:, 1], e2[keep]) < TOL["fp64"]
+    ref = oracle.moments(e1[keep], e2[keep], weights=np.abs(psi[keep]) ** 2, e3=e3[keep])
+    assert abs(res1["e_p1"] - ref["e_p1"]) < TOL["fp64"] * abs(ref["h1"])
+    res2, e123 = m.lanczos_moments_p2(cuda(spins[keep]), exact=True)
+    e123 = e123.cpu().numpy()
+    for k, e in enumerate((e1, e2, e3)):
+        assert max_rel_err(e123[:, k], e[keep]) < TOL["fp64"]
+    assert abs(res2["e_p2"] - ref["e_p2"]) < TOL["fp64"] * abs(ref["h1"])
+
+
+def test_composed_e2_6x6_m16_fp32():
+    """6x6 with 16 hidden units: fused E_loc, no register two-hop kernel."""
+    w = dataclasses.replace(WORKLOADS["6x6_fp32_lanczos"], n_hidden=16)
+    p = stress_params(w, 0.05, 12)
+    om = oracle.Model.from_workload(w)
+    sp = random_sz0_spins(w.N, 3, 31)
+    m = make(w, p)
+    res, e12 = m.lanczos_moments(cuda(sp), exact=False)
+    e12 = e12.cpu().numpy()
+    assert max_rel_err(e12[:, 0], oracle.eloc_direct(om, p, sp)) < TOL["fp32"]
+    assert max_rel_err(e12[:, 1], oracle.e2_direct(om, p, sp)) < TOL["fp32"]
+    assert res["n"] == 3
