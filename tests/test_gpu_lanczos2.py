@@ -218,3 +218,35 @@ def test_composed_e2_6x6_m16_fp32():
     assert max_rel_err(e12[:, 0], oracle.eloc_direct(om, p, sp)) < TOL["fp32"]
     assert max_rel_err(e12[:, 1], oracle.e2_direct(om, p, sp)) < TOL["fp32"]
     assert res["n"] == 3
+
+
+def test_p2_single_configuration_and_errors():
+    """S = 1 (one configuration, ragged in every tile) agrees with the stored
+    oracle values; S = 0, a bad exact flag and a short workspace are rejected
+    before any launch."""
+    import ctypes as C
+    from paper_2206_14307_amd import NQSError
+    from paper_2206_14307_amd.nqs import NQS_ERR_ARG, OP, Moments2, _ptr, _stream
+    g = json.load(open(GOLDEN))
+    w = dataclasses.replace(WORKLOADS["6x6_fp32_lanczos"], n_hidden=8)
+    p = stress_params(w, 0.05, 4)
+    sp = np.array(g["spins"], np.int8)[:1]
+    m = make(w, p)
+    res, e123 = m.lanczos_moments_p2(cuda(sp), exact=False)
+    want = np.array([complex(*g["e3"][0])])
+    assert max_rel_err(e123.cpu().numpy()[:, 2], want) < TOL["fp32"]
+    with pytest.raises(NQSError):
+        m.lanczos_moments_p2(cuda(sp[:0]), exact=False)
+    out = Moments2()
+    spd = cuda(sp)
+    need = int(m.lib.nqs_workspace_bytes(m._ctx, OP["moments2"], 1))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    st = m.lib.nqs_lanczos_moments_p2(m._ctx, _ptr(spd), 1, 2, None, C.byref(out), _ptr(ws),
+                                      need, _stream())
+    assert st == NQS_ERR_ARG
+    st = m.lib.nqs_lanczos_moments_p2(m._ctx, _ptr(spd), 1, 0, None, C.byref(out), _ptr(ws),
+                                      need - 1, _stream())
+    assert st == NQS_ERR_ARG
+    st = m.lib.nqs_lanczos_moments_p2(m._ctx, _ptr(spd), 1, 0, None, None, _ptr(ws), need,
+                                      _stream())
+    assert st == NQS_ERR_ARG
