@@ -250,3 +250,44 @@ def test_p2_single_configuration_and_errors():
     st = m.lib.nqs_lanczos_moments_p2(m._ctx, _ptr(spd), 1, 0, None, None, _ptr(ws), need,
                                       _stream())
     assert st == NQS_ERR_ARG
+
+
+GOLDEN72 = os.path.join(os.path.dirname(__file__), "golden", "e3_6x6_m72_striped.json")
+
+
+def test_p2_full_size_bench_launch():
+    """The launch bench.py times: the first 256 configurations of the 6x6
+    Lanczos workload's random set (M = 72, its parameters), plus one striped
+    configuration whose e1, e2, e3 the oracle stored.  Sampled configurations
+    of the 256 are checked by the composition that holds at any size,
+    e3 = H_ss e2 + sum_b (J_b/2) psi(s^b)/psi(s) e2(s^b), with nqs_logpsi and
+    nqs_lanczos_moments on the exchange neighbours (each oracle-checked
+    elsewhere)."""
+    from workloads import random_sz0_spins_fast
+    g = json.load(open(GOLDEN72))
+    w = WORKLOADS["6x6_fp32_lanczos"]
+    p = draw_params(w)
+    spins = random_sz0_spins_fast(w.N, w.n_chains * w.n_per_chain, 3003)[:256]
+    sp = np.concatenate([spins, np.array(g["spins"], np.int8)])
+    m = make(w, p)
+    res, e123 = m.lanczos_moments_p2(cuda(sp), exact=False)
+    e123 = e123.cpu().numpy()
+    for k, key in enumerate(("e1", "e2", "e3")):
+        want = complex(*g[key][0])
+        assert abs(e123[-1, k] - want) / max(1.0, abs(want)) < TOL["fp32"], key
+    om = oracle.Model.from_workload(w)
+    bonds, J = om.lat.bonds, np.asarray(om.bond_J, np.float64)
+    lp0 = m.logpsi(cuda(sp)).cpu().numpy()
+    for r in (0, 97, 255):
+        s = sp[r]
+        anti = np.nonzero(s[bonds[:, 0]] != s[bonds[:, 1]])[0]
+        nb = np.repeat(s[None, :], len(anti), axis=0)
+        for k, b in enumerate(anti):
+            i, j = bonds[b]
+            nb[k, i], nb[k, j] = s[j], s[i]
+        lpn = m.logpsi(cuda(nb)).cpu().numpy()
+        e2n = m.lanczos_moments(cuda(nb), exact=False)[1].cpu().numpy()[:, 1]
+        diag = 0.25 * float((J * s[bonds[:, 0]] * s[bonds[:, 1]]).sum())
+        e3 = diag * e123[r, 1] + (0.5 * J[anti] * np.exp(lpn - lp0[r]) * e2n).sum()
+        assert abs(e123[r, 2] - e3) <= TOL["fp32"] * max(1.0, abs(e3)), (r, e123[r, 2], e3)
+    assert not res["degenerate"] and res["e_p2"] <= res["e_p1"] <= res["h1"]
