@@ -8,8 +8,8 @@
 //  1. column means of O, then O_bar written transposed as separate real and
 //     imaginary planes [P][S] (unit-stride sample axis for the MFMA operands);
 //  2. Gram T = O_bar O_bar^H + lambda I on 16x16x4 MFMA (FP32 for complex64
-//     O, FP64 for complex128), complex product as four real products,
-//     lower block triangle only, stored in FP64;
+//     O, on LDS-staged 128 x 128 tiles; FP64 for complex128), complex product
+//     as four real products, lower block triangle only, stored in FP64;
 //  3. blocked right-looking FP64 Cholesky T = L L^H with 32 x 32 blocks:
 //     diagonal factorisation in LDS, panel triangular solve, trailing
 //     Hermitian update on FP64 MFMA;
@@ -173,6 +173,120 @@ __global__ __launch_bounds__(256) void gram_kernel(const RG* __restrict__ Tre,
       for (int r = 0; r < 4; ++r) {
         const int64_t row = I * kB + 16 * a + out_row<RG>(q, r);
         const int64_t col = J * kB + 16 * b + c;
+        double vr = (double)cr[a][b][r], vi = (double)ci[a][b][r];
+        if (row == col) vr += lambda;
+        T[(row * S32 + col) * 2] = vr;
+        T[(row * S32 + col) * 2 + 1] = vi;
+      }
+}
+
+// FP32 Gram on 128 x 128 output tiles, one workgroup of four wavefronts per
+// lower tile (each wavefront a 64 x 64 quarter, 4 x 4 MFMA tiles of 16 x 16
+// for each of the real and imaginary parts).  The two row panels of the tile
+// go through LDS in stages of kGK sample-axis columns, double-buffered: the
+// next stage's global loads are issued before the current stage's MFMAs.
+// Per k, a panel row of 128 values is stored as [half][c][a] (row
+// 64 half + 16 a + c at 64 half + 4 c + a) so that lane (q, c) reads its four
+// operands a = 0..3 with one 16-byte LDS load; kGP pads the k rows apart.
+// Only 32 x 32 blocks on or below the block diagonal are written.
+constexpr int kGT = 128, kGK = 8, kGP = kGT + 4;
+
+__global__ __launch_bounds__(256) void gram_tile_kernel(const float* __restrict__ Tre,
+                                                        const float* __restrict__ Tim, int64_t P4,
+                                                        int64_t S32, int64_t ntile, double lambda,
+                                                        double* __restrict__ T) {
+  __shared__ __align__(16) float As[2][2][kGK][kGP];   // [buffer][re, im][k][row slot]
+  __shared__ __align__(16) float Bs[2][2][kGK][kGP];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, q = lane >> 4, c = lane & 15;
+  const int wy = wv >> 1, wx = wv & 1;
+  int64_t I, J;
+  tri_index((int64_t)blockIdx.x, I, J);
+  (void)ntile;
+  const int64_t rowA = I * kGT, rowB = J * kGT;
+
+  // stage loader: 1024 float4 per stage (A/B x re/im x kGK x 32), four per thread
+  float4 pre[4];
+  auto load_stage = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + 256 * i;
+      const int ab = idx >> 9, rem = idx & 511, pl = rem >> 8, k = (rem >> 5) & 7, r4 = rem & 31;
+      const int64_t row = (ab ? rowB : rowA) + 4 * r4, kk = k0 + k;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (kk < P4 && row < S32)
+        v = *reinterpret_cast<const float4*>((pl ? Tim : Tre) + kk * S32 + row);
+      pre[i] = v;
+    }
+  };
+  auto store_stage = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + 256 * i;
+      const int ab = idx >> 9, rem = idx & 511, pl = rem >> 8, k = (rem >> 5) & 7, r4 = rem & 31;
+      float* dst = ab ? &Bs[buf][pl][k][0] : &As[buf][pl][k][0];
+      const float vals[4] = {pre[i].x, pre[i].y, pre[i].z, pre[i].w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 4 * r4 + e;                       // tile row 0..127
+        dst[64 * (r >> 6) + 4 * (r & 15) + ((r >> 4) & 3)] = vals[e];
+      }
+    }
+  };
+
+  f32x4 cr[4][4], ci[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      cr[a][b] = f32x4{0, 0, 0, 0};
+      ci[a][b] = f32x4{0, 0, 0, 0};
+    }
+  const int64_t nst = (P4 + kGK - 1) / kGK;
+  load_stage(0);
+  store_stage(0);
+  __syncthreads();
+  for (int64_t st = 0; st < nst; ++st) {
+    const int cur = (int)(st & 1);
+    if (st + 1 < nst) load_stage((st + 1) * kGK);
+#pragma unroll
+    for (int ks = 0; ks < kGK; ks += 4) {
+      const float4 a_r = *reinterpret_cast<const float4*>(&As[cur][0][ks + q][64 * wy + 4 * c]);
+      const float4 a_i = *reinterpret_cast<const float4*>(&As[cur][1][ks + q][64 * wy + 4 * c]);
+      const float4 b_r = *reinterpret_cast<const float4*>(&Bs[cur][0][ks + q][64 * wx + 4 * c]);
+      const float4 b_i = *reinterpret_cast<const float4*>(&Bs[cur][1][ks + q][64 * wx + 4 * c]);
+      const float ar[4] = {a_r.x, a_r.y, a_r.z, a_r.w}, ai[4] = {a_i.x, a_i.y, a_i.z, a_i.w};
+      const float br[4] = {b_r.x, b_r.y, b_r.z, b_r.w}, bi[4] = {b_i.x, b_i.y, b_i.z, b_i.w};
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) cr[a][b] = mma(ar[a], br[b], cr[a][b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) ci[a][b] = mma(ai[a], br[b], ci[a][b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) cr[a][b] = mma(ai[a], bi[b], cr[a][b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) ci[a][b] = mma(-ar[a], bi[b], ci[a][b]);
+    }
+    if (st + 1 < nst) {
+      store_stage(cur ^ 1);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = rowA + 64 * wy + 16 * a + out_row<float>(q, r);
+        const int64_t col = rowB + 64 * wx + 16 * b + c;
+        if (row >= S32 || col >= S32 || row / kB < col / kB) continue;
         double vr = (double)cr[a][b][r], vi = (double)ci[a][b][r];
         if (row == col) vr += lambda;
         T[(row * S32 + col) * 2] = vr;
@@ -447,7 +561,13 @@ hipError_t sr_run(const nqs_ctx* c, const void* Ov, const double* el, int64_t S,
   eps_kernel<<<1, 1024, 0, st>>>(el, S, S32, v);
   const int64_t ntri = nblk * (nblk + 1) / 2;
   prof_begin(c, K_GRAM, st);
-  gram_kernel<RG><<<(unsigned)((ntri + 3) / 4), 256, 0, st>>>(Tre, Tim, P4, S32, nblk, lambda, T);
+  if constexpr (sizeof(RG) == 4) {
+    const int64_t ntile = (S32 + kGT - 1) / kGT;
+    gram_tile_kernel<<<(unsigned)(ntile * (ntile + 1) / 2), 256, 0, st>>>(
+        (const float*)Tre, (const float*)Tim, P4, S32, ntile, lambda, T);
+  } else {
+    gram_kernel<RG><<<(unsigned)((ntri + 3) / 4), 256, 0, st>>>(Tre, Tim, P4, S32, nblk, lambda, T);
+  }
   prof_end(c, K_GRAM, st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   prof_begin(c, K_CHOL, st);

@@ -49,11 +49,15 @@ def test_sr_fp64_push_through(c1_inputs, S):
     assert np.linalg.norm(got - ref_s) < 1e-9 * np.linalg.norm(ref_s)
 
 
-def test_sr_fp32_6x6():
+@pytest.mark.parametrize("S", [150, 300])
+def test_sr_fp32_6x6(S):
+    """FP32 Gram on 128 x 128 tiles: S = 150 and 300 give 2 and 3 tile rows,
+    off-diagonal tiles and a partial last tile; P = 628 ends in a partial
+    8-column stage."""
     w = dataclasses.replace(WORKLOADS["6x6_fp32_lanczos"], n_hidden=16)
     p = stress_params(w, 0.05, 5)
     om = oracle.Model.from_workload(w)
-    spins = random_sz0_spins(w.N, 150, 6)
+    spins = random_sz0_spins(w.N, S, 6)
     O = oracle.logderiv(om, p, spins).astype(np.complex64)
     el = oracle.eloc_direct(om, p, spins)
     m = make(w)
