@@ -544,7 +544,9 @@ def leg_sr(name="10x10_m400", S=32768, steps=1):
           "unit": "GB/s", "frac": 2.0 * o_bytes * iters / (ms_cg / 1e3) / 1e9 / PEAK_HBM_GBS,
           "bytes_per_iteration": 2.0 * o_bytes}
     flops_gram = 8.0 * S * S * m.P / 2
-    flops_chol = 8.0 * S ** 3 / 3
+    # complex Cholesky: S^3/6 complex multiply-adds = (4/3) S^3 real flops, plus
+    # the two triangular solves (S^2/2 complex multiply-adds each)
+    flops_chol = 4.0 * S ** 3 / 3 + 8.0 * S * S
     pk_gram = 78.6 if w.precision == "fp64" else 157.3
     return {"workload": name, "S": S, "P": m.P, "precision": w.precision,
             "ms_eloc": ms_e, "ms_grad": ms_g, "ms_sr": ms_sr,

@@ -11,8 +11,9 @@
 //     O, on LDS-staged 128 x 128 tiles; FP64 for complex128), complex product
 //     as four real products, lower block triangle only, stored in FP64;
 //  3. blocked right-looking FP64 Cholesky T = L L^H with 32 x 32 blocks:
-//     diagonal factorisation in LDS, panel triangular solve, trailing
-//     Hermitian update on FP64 MFMA;
+//     diagonal factorisation in LDS, panel triangular solve, Hermitian
+//     updates on FP64 MFMA (within a panel of 4 block columns per column,
+//     then one rank-128 update of the trailing matrix per panel);
 //  4. L y = eps, L^H x = y, dtheta = -dtau O_bar^H x.
 // S is padded to a multiple of 32 with zero rows (their T block is lambda I
 // and their eps is 0, so they drop out of x and dtheta).
@@ -28,6 +29,7 @@ namespace nqs {
 namespace {
 
 constexpr int kB = 32;   // Cholesky / Gram block
+constexpr int kPanel = 4; // block columns per Cholesky panel (one trailing update each)
 
 __device__ __forceinline__ f64x4 mma(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -378,17 +380,36 @@ __global__ __launch_bounds__(256) void trsm_panel_kernel(double* __restrict__ T,
 }
 
 // Trailing update: A_IJ -= X_I X_J^H for I >= J > k (X = panel block column k).
+// Hermitian rank-(32 nk) update T[I][J] -= L[I][K] L[J][K]^H over the block
+// columns K = kc0 .. kc0 + nk - 1, one wavefront per 32 x 32 output block.
+// jn = 0: every block I >= J >= j0 (the trailing triangle); jn > 0: only the
+// block columns J = j0 .. j0 + jn - 1 (the rest of the current panel), all
+// I >= J.
 __global__ __launch_bounds__(256) void herk_update_kernel(double* __restrict__ T, int64_t S32,
-                                                          int64_t k, int64_t nblk) {
+                                                          int64_t kc0, int nk, int64_t j0, int jn,
+                                                          int64_t nblk) {
   const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
-  const int64_t m = nblk - k - 1;
-  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= m * (m + 1) / 2) return;
-  int64_t I, J;
-  tri_index(t, I, J);
-  I += k + 1;
-  J += k + 1;
-  const int64_t kb = k * kB;
+  int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  int64_t I = -1, J = -1;
+  if (jn == 0) {
+    const int64_t m = nblk - j0;
+    if (t >= m * (m + 1) / 2) return;
+    tri_index(t, I, J);
+    I += j0;
+    J += j0;
+  } else {
+    for (int jj = 0; jj < jn; ++jj) {
+      const int64_t cnt = nblk - (j0 + jj);
+      if (t < cnt) {
+        J = j0 + jj;
+        I = J + t;
+        break;
+      }
+      t -= cnt;
+    }
+    if (J < 0) return;
+  }
+  const int64_t kb = kc0 * kB;
   f64x4 cr[2][2], ci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -397,7 +418,7 @@ __global__ __launch_bounds__(256) void herk_update_kernel(double* __restrict__ T
       cr[a][b] = f64x4{0, 0, 0, 0};
       ci[a][b] = f64x4{0, 0, 0, 0};
     }
-  for (int k0 = 0; k0 < kB; k0 += 4) {
+  for (int k0 = 0; k0 < nk * kB; k0 += 4) {
     double xr[2], xi[2], yr[2], yi[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -571,15 +592,29 @@ hipError_t sr_run(const nqs_ctx* c, const void* Ov, const double* el, int64_t S,
   prof_end(c, K_GRAM, st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   prof_begin(c, K_CHOL, st);
-  for (int64_t k = 0; k < nblk; ++k) {
-    potrf_diag_kernel<<<1, 256, 0, st>>>(T, S32, k, flag);
-    const int64_t rows = S32 - (k + 1) * kB;
-    if (rows > 0) {
-      trsm_panel_kernel<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(T, S32, k);
-      const int64_t m = nblk - k - 1, nt = m * (m + 1) / 2;
-      herk_update_kernel<<<(unsigned)((nt + 3) / 4), 256, 0, st>>>(T, S32, k, nblk);
+  // right-looking, in panels of kPanel block columns: each block column is
+  // factored, solved below and applied to the rest of its panel; the panel
+  // as a whole then updates the trailing matrix in one rank-(32 kPanel) pass
+  for (int64_t K0 = 0; K0 < nblk; K0 += kPanel) {
+    const int64_t K1 = std::min<int64_t>(K0 + kPanel, nblk);
+    for (int64_t k = K0; k < K1; ++k) {
+      potrf_diag_kernel<<<1, 256, 0, st>>>(T, S32, k, flag);
+      const int64_t rows = S32 - (k + 1) * kB;
+      if (rows > 0) trsm_panel_kernel<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(T, S32, k);
+      if (k + 1 < K1) {
+        const int jn = (int)(K1 - k - 1);
+        int64_t nt = 0;
+        for (int jj = 0; jj < jn; ++jj) nt += nblk - (k + 1 + jj);
+        herk_update_kernel<<<(unsigned)((nt + 3) / 4), 256, 0, st>>>(T, S32, k, 1, k + 1, jn, nblk);
+      }
+      if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (K1 < nblk) {
+      const int64_t m = nblk - K1, nt = m * (m + 1) / 2;
+      herk_update_kernel<<<(unsigned)((nt + 3) / 4), 256, 0, st>>>(T, S32, K0, (int)(K1 - K0), K1,
+                                                                  0, nblk);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   for (int64_t k = 0; k < nblk; ++k) {
     fsolve_diag_kernel<<<1, 64, 0, st>>>(T, S32, k, v);
