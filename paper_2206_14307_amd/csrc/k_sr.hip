@@ -455,21 +455,46 @@ __global__ __launch_bounds__(256) void herk_update_kernel(double* __restrict__ T
 
 // ------------------------------------------------------------------ solves
 // L y = v on block k (single thread; the block is small)
-__global__ void fsolve_diag_kernel(const double* __restrict__ T, int64_t S32, int64_t k,
-                                   double* __restrict__ v) {
-  if (threadIdx.x != 0) return;
+// Diagonal-block triangular solves: the 32 x 32 block goes to LDS, lane i
+// holds v_i, and the substitution runs column by column (lane j finishes its
+// unknown, the others subtract its contribution), 32 steps of one wavefront.
+__device__ __forceinline__ void load_diag_block(const double* __restrict__ T, int64_t S32,
+                                                int64_t kb, double (*lr)[kB + 1],
+                                                double (*li)[kB + 1]) {
+  for (int e = threadIdx.x; e < kB * kB; e += blockDim.x) {
+    const int i = e / kB, j = e % kB;
+    lr[i][j] = T[((kb + i) * S32 + kb + j) * 2];
+    li[i][j] = T[((kb + i) * S32 + kb + j) * 2 + 1];
+  }
+  __syncthreads();
+}
+
+// L y = v on diagonal block k (y overwrites v)
+__global__ __launch_bounds__(64) void fsolve_diag_kernel(const double* __restrict__ T, int64_t S32,
+                                                         int64_t k, double* __restrict__ v) {
+  __shared__ double lr[kB][kB + 1], li[kB][kB + 1];
+  const int t = threadIdx.x;
   const int64_t kb = k * kB;
+  load_diag_block(T, S32, kb, lr, li);
+  double vr = 0.0, vi = 0.0;
+  if (t < kB) {
+    vr = v[2 * (kb + t)];
+    vi = v[2 * (kb + t) + 1];
+  }
   for (int j = 0; j < kB; ++j) {
-    double vr = v[2 * (kb + j)], vi = v[2 * (kb + j) + 1];
-    for (int l = 0; l < j; ++l) {
-      const double Lr = T[((kb + j) * S32 + kb + l) * 2], Li = T[((kb + j) * S32 + kb + l) * 2 + 1];
-      const double yr = v[2 * (kb + l)], yi = v[2 * (kb + l) + 1];
-      vr -= Lr * yr - Li * yi;
-      vi -= Lr * yi + Li * yr;
+    if (t == j) {
+      vr /= lr[j][j];
+      vi /= lr[j][j];
     }
-    const double d = T[((kb + j) * S32 + kb + j) * 2];
-    v[2 * (kb + j)] = vr / d;
-    v[2 * (kb + j) + 1] = vi / d;
+    const double yr = __shfl(vr, j, 64), yi = __shfl(vi, j, 64);
+    if (t > j && t < kB) {
+      vr -= lr[t][j] * yr - li[t][j] * yi;
+      vi -= lr[t][j] * yi + li[t][j] * yr;
+    }
+  }
+  if (t < kB) {
+    v[2 * (kb + t)] = vr;
+    v[2 * (kb + t) + 1] = vi;
   }
 }
 
@@ -491,22 +516,33 @@ __global__ void fsolve_update_kernel(const double* __restrict__ T, int64_t S32, 
 }
 
 // L^H x = v on block k (single thread)
-__global__ void bsolve_diag_kernel(const double* __restrict__ T, int64_t S32, int64_t k,
-                                   double* __restrict__ v) {
-  if (threadIdx.x != 0) return;
+// L^H x = v on diagonal block k (x overwrites v)
+__global__ __launch_bounds__(64) void bsolve_diag_kernel(const double* __restrict__ T, int64_t S32,
+                                                         int64_t k, double* __restrict__ v) {
+  __shared__ double lr[kB][kB + 1], li[kB][kB + 1];
+  const int t = threadIdx.x;
   const int64_t kb = k * kB;
+  load_diag_block(T, S32, kb, lr, li);
+  double vr = 0.0, vi = 0.0;
+  if (t < kB) {
+    vr = v[2 * (kb + t)];
+    vi = v[2 * (kb + t) + 1];
+  }
   for (int j = kB - 1; j >= 0; --j) {
-    double vr = v[2 * (kb + j)], vi = v[2 * (kb + j) + 1];
-    for (int l = j + 1; l < kB; ++l) {
-      // v_j -= conj(L[l][j]) x_l
-      const double Lr = T[((kb + l) * S32 + kb + j) * 2], Li = T[((kb + l) * S32 + kb + j) * 2 + 1];
-      const double xr = v[2 * (kb + l)], xi = v[2 * (kb + l) + 1];
-      vr -= Lr * xr + Li * xi;
-      vi -= Lr * xi - Li * xr;
+    if (t == j) {
+      vr /= lr[j][j];
+      vi /= lr[j][j];
     }
-    const double d = T[((kb + j) * S32 + kb + j) * 2];
-    v[2 * (kb + j)] = vr / d;
-    v[2 * (kb + j) + 1] = vi / d;
+    const double xr = __shfl(vr, j, 64), xi = __shfl(vi, j, 64);
+    if (t < j) {
+      // v_t -= conj(L[j][t]) x_j
+      vr -= lr[j][t] * xr + li[j][t] * xi;
+      vi -= lr[j][t] * xi - li[j][t] * xr;
+    }
+  }
+  if (t < kB) {
+    v[2 * (kb + t)] = vr;
+    v[2 * (kb + t) + 1] = vi;
   }
 }
 
