@@ -615,10 +615,17 @@ def main():
     torch.cuda.synchronize()
     t_sample = time.perf_counter() - t0
     nskip = int(nskip.item())
+    props = w.n_chains * (20 * w.N + w.n_per_chain * nskip)
+    acc = float(acc_rate.mean().item())
+    # per proposal: G K M exchange factors (13 flops each, as for E_loc) and, if
+    # accepted, the tanh addition (t - T)/(1 - t T) of every (g, h): ~20 flops
+    fl_s = props * w.G * w.n_rbm * w.n_hidden * (13.0 + 20.0 * acc)
     sample_leg = {"chains": w.n_chains, "per_chain": w.n_per_chain, "burn_in": 20 * w.N,
-                  "n_skip": nskip, "acceptance": float(acc_rate.mean().item()),
-                  "seconds": t_sample,
-                  "proposals_per_s": w.n_chains * (20 * w.N + w.n_per_chain * nskip) / t_sample}
+                  "n_skip": nskip, "acceptance": acc, "seconds": t_sample,
+                  "proposals_per_s": props / t_sample,
+                  "roofline": {"bound": "alu", "achieved": fl_s / t_sample / 1e12, "peak": 157.3,
+                               "unit": "TFLOP/s", "frac": fl_s / t_sample / 1e12 / 157.3,
+                               "flops_per_factor": "13 + 20 x acceptance"}}
     log(f"sampled {S} configurations in {t_sample:.2f} s (N_skip {nskip})")
     spins_np = sp.cpu().numpy()
     lp = torch.empty(S, dtype=torch.complex128, device="cuda")

@@ -227,6 +227,7 @@ __global__ __launch_bounds__(640) void sample_reg_kernel(
     int64_t* __restrict__ acc_out, int8_t* __restrict__ cur_spins) {
   constexpr int MH = M / SPLIT;                  // hidden units per lane
   __shared__ double red[32];
+  extern __shared__ uint8_t pinv[];              // [G][N] inverse permutations (G N bytes)
   const int64_t c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = (blockDim.x + 63) >> 6;
   const int g = SPLIT == 2 ? 32 * wv + (lane & 31) : tid;
@@ -257,6 +258,9 @@ __global__ __launch_bounds__(640) void sample_reg_kernel(
     wr = wc[2 * gg];
     wi = wc[2 * gg + 1];
   }
+  // the table lookups of every proposal read LDS instead of L2
+  for (int e = tid; e < G * N; e += blockDim.x) pinv[e] = perminv[e];
+  __syncthreads();
   int64_t acc = 0;
   for (int r = 0; r < n_prop && valid; ++r) {
     uint64_t rnd[4];
@@ -265,7 +269,7 @@ __global__ __launch_bounds__(640) void sample_reg_kernel(
     const int kdn = (int)(((rnd[1] >> 11) * (uint64_t)half) >> 53);
     const int i = select128(lo, hi, kup);
     const int j = select128(~lo & nmask_lo, ~hi & nmask_hi, kdn);
-    const int l1 = perminv[(size_t)gg * N + i], l2 = perminv[(size_t)gg * N + j];
+    const int l1 = pinv[gg * N + i], l2 = pinv[gg * N + j];
     const R* Trow = Tpair + (((size_t)l1 * N + l2) * M + h0) * 2;
     R pr = 1, pi = 0, qr = 1, qi = 0;
 #pragma unroll
@@ -361,7 +365,7 @@ hipError_t launch_reg(const nqs_ctx* c, int64_t n, const void* t, const void* w,
                       hipStream_t st) {
   const int threads = SPLIT == 2 ? 64 * ((c->G + 31) / 32) : 64 * ((c->G + 63) / 64);
   if (threads > 640) return hipErrorNotSupported;
-  sample_reg_kernel<R, M, SPLIT><<<(unsigned)n, threads, 0, st>>>(
+  sample_reg_kernel<R, M, SPLIT><<<(unsigned)n, threads, (size_t)c->G * c->N, st>>>(
       c->N, c->G, c->n_htiles, c->dev.perminv, (const R*)c->par.Tpair, (const R*)c->par.Fpair,
       (const R*)t, (const R*)w, state, cnt, phase, p0, ns, seed, spins_out, n_per_chain, acc,
       cur);
