@@ -228,6 +228,7 @@ __global__ __launch_bounds__(640) void sample_reg_kernel(
   constexpr int MH = M / SPLIT;                  // hidden units per lane
   __shared__ double red[32];
   extern __shared__ uint8_t pinv[];              // [G][N] inverse permutations (G N bytes)
+  __shared__ uint64_t rbuf[64][3];               // random words of the next 64 proposals
   const int64_t c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = (blockDim.x + 63) >> 6;
   const int g = SPLIT == 2 ? 32 * wv + (lane & 31) : tid;
@@ -263,8 +264,20 @@ __global__ __launch_bounds__(640) void sample_reg_kernel(
   __syncthreads();
   int64_t acc = 0;
   for (int r = 0; r < n_prop && valid; ++r) {
-    uint64_t rnd[4];
-    philox4x64_10(ctr, 0, 0, 0, seed, id, rnd);
+    // Philox depends only on the proposal index: one wavefront draws the words
+    // of 64 proposals at once (counters ctr .. ctr + 63), every wave reads them
+    if ((r & 63) == 0) {
+      __syncthreads();
+      if (tid < 64) {
+        uint64_t rr[4];
+        philox4x64_10(ctr + (uint64_t)tid, 0, 0, 0, seed, id, rr);
+        rbuf[tid][0] = rr[0];
+        rbuf[tid][1] = rr[1];
+        rbuf[tid][2] = rr[2];
+      }
+      __syncthreads();
+    }
+    const uint64_t rnd[3] = {rbuf[r & 63][0], rbuf[r & 63][1], rbuf[r & 63][2]};
     const int kup = (int)(((rnd[0] >> 11) * (uint64_t)half) >> 53);
     const int kdn = (int)(((rnd[1] >> 11) * (uint64_t)half) >> 53);
     const int i = select128(lo, hi, kup);
