@@ -275,8 +275,7 @@ def leg_lanczos(steps=2):
            "roofline": {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12, "peak": 157.3,
                         "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / 1e12 / 157.3,
                         "flops_per_factor": 13}}
-    # the wide models' e2 (neighbours through the wide E_loc kernel), on a small
-    # sample of their workloads
+    # the wide models' e2, on a small sample of their workloads
     out["wide_models"] = {}
     for name, Sw in (("8x8_k4_m256", 64), ("10x10_m400", 16)):
         ww = WORKLOADS[name]
@@ -284,13 +283,10 @@ def leg_lanczos(steps=2):
         mw.set_params(torch.from_numpy(draw_params(ww).reshape(-1)))
         spw = torch.from_numpy(random_sz0_spins_fast(ww.N, Sw, 3003)).cuda()
         msw = timed(lambda: mw.lanczos_moments(spw, exact=False, want_e1e2=False), 1, 1)
-        # e2 from the neighbours' E_loc (fused / wide kernels): one-hop factors of
-        # the configurations and of every exchange neighbour
-        bw = square_bonds(ww.L)
-        xw = spw.cpu().numpy()
-        nbw = neighbours(xw, bw)
-        hw = sum(int((y[:, bw[:, 0]] != y[:, bw[:, 1]]).sum()) for y in (xw, nbw))
-        fw = float(hw) * ww.G * ww.n_rbm * ww.n_hidden
+        # e2 from the exchange neighbours through the wide E_loc kernel, each
+        # with its parent's unordered-pair bond list: the same factor products
+        # as the two-hop kernels evaluate
+        fw = float(twohop_hops(spw.cpu().numpy(), square_bonds(ww.L))) * ww.G * ww.n_rbm * ww.n_hidden
         out["wide_models"][name] = {"S": Sw, "ms": msw, "ms_per_config": msw / Sw, "factors": fw,
                                     "factors_per_s": fw / (msw / 1e3),
                                     "frac": 13.0 * fw / (msw / 1e3) / 1e12 / 157.3}

@@ -118,6 +118,7 @@ struct Work {
   double* nb_e1e2 = nullptr;       // [chunk][2] complex e1, e2 of the neighbours
   int32_t* nb_cnt = nullptr;       // [n_out] antiparallel bonds per configuration
   int32_t* nb_off = nullptr;       // [n_out + 1] their exclusive scan
+  int16_t* nb_parent = nullptr;    // [chunk] bond exchanged to make each neighbour row
   int64_t n_out = 0;               // configurations per neighbour chunk
   int64_t chunk = 1;
   size_t bytes = 0;
@@ -136,7 +137,7 @@ Work plan(const nqs_ctx* c, int op, int64_t S, void* ws) {
   if (op == NQS_OP_MOMENTS2) wk.e3 = (double*)cv.take((size_t)std::max<int64_t>(S, 1) * 16);
   if (composed_moments(c, op)) {
     // chunk = neighbour configurations per E_loc launch (at most NB per configuration)
-    const size_t b = fused_part_bytes(c) + c->N + 48;
+    const size_t b = fused_part_bytes(c) + c->N + 50;
     int64_t ch = (int64_t)std::max<size_t>(1, kChunkBytes / b);
     ch = std::max<int64_t>(std::min<int64_t>(ch, std::max<int64_t>(S, 1) * c->NB), c->NB);
     wk.chunk = ch;
@@ -147,6 +148,7 @@ Work plan(const nqs_ctx* c, int op, int64_t S, void* ws) {
     wk.nb_e1e2 = (double*)cv.take((size_t)ch * 32);
     wk.nb_cnt = (int32_t*)cv.take((size_t)wk.n_out * 4);
     wk.nb_off = (int32_t*)cv.take((size_t)(wk.n_out + 1) * 4);
+    wk.nb_parent = (int16_t*)cv.take((size_t)ch * 2);
     wk.bytes = cv.off;
     return wk;
   }
@@ -531,7 +533,7 @@ hipError_t eloc_fused_any(nqs_ctx* c, const int8_t* sp, int64_t n, double* part,
 // Neighbour rows of n configurations into wk.nb_spins (bond order; wk.nb_off
 // their offsets); *total = their number (reads it back: synchronises).
 hipError_t expand_neighbours(nqs_ctx* c, const Work& wk, const int8_t* sp, int64_t n,
-                             int32_t* total, hipStream_t st) {
+                             int32_t* total, hipStream_t st, int16_t* parent = nullptr) {
   *total = 0;
   hipError_t e = NQS_RUN(c, K_HOP3, st, launch_nb_count(c, sp, n, wk.nb_cnt, st));
   if (e == hipSuccess) e = NQS_RUN(c, K_HOP3, st, launch_nb_scan(wk.nb_cnt, n, wk.nb_off, st));
@@ -539,7 +541,10 @@ hipError_t expand_neighbours(nqs_ctx* c, const Work& wk, const int8_t* sp, int64
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return e;
   if (*total < 0 || *total > wk.chunk) return hipErrorInvalidValue;
-  if (*total > 0) e = NQS_RUN(c, K_HOP3, st, launch_nb_write(c, sp, n, wk.nb_off, wk.nb_spins, st));
+  if (*total > 0)
+    e = NQS_RUN(c, K_HOP3, st,
+                parent ? launch_nb_write_parent(c, sp, n, wk.nb_off, wk.nb_spins, parent, st)
+                       : launch_nb_write(c, sp, n, wk.nb_off, wk.nb_spins, st));
   return e;
 }
 
@@ -602,18 +607,34 @@ nqs_status nqs_lanczos_moments(nqs_ctx* c, const int8_t* spins, int64_t S, int e
     const int8_t* sp = spins + s0 * c->N;
     double* lp = wk.logpsi + 2 * s0;
     double* e12 = wk.e1e2 + 4 * s0;
+    // wide models: each neighbour's bond list is its parent's unordered-pair
+    // list and the neighbours contribute path sums (no division by their psi)
+    const bool pairs = !eloc_fused_supported(c);
     e = eloc_fused_any(c, sp, n, wk.partial, lp, e12, 4, st);
     int32_t total = 0;
-    if (e == hipSuccess) e = expand_neighbours(c, wk, sp, n, &total, st);
+    if (e == hipSuccess) e = expand_neighbours(c, wk, sp, n, &total, st, pairs ? wk.nb_parent : nullptr);
     if (e == hipErrorInvalidValue)
       return fail(c, NQS_ERR_DEVICE, "neighbour count " + std::to_string(total) +
                                          " exceeds the chunk " + std::to_string(wk.chunk));
-    if (e == hipSuccess && total > 0)
-      e = eloc_fused_any(c, wk.nb_spins, total, wk.partial, wk.nb_lp, wk.nb_e1e2, 4, st);
-    if (e == hipSuccess)
-      e = NQS_RUN(c, K_HOP3, st,
-                  launch_hop_combine(c, sp, n, wk.nb_off, lp, e12, 4, wk.nb_lp, wk.nb_e1e2, 4,
-                                     e12 + 2, 4, st));
+    if (pairs) {
+      if (e == hipSuccess && total > 0)
+        e = NQS_RUN(c, K_ELOC, st,
+                    launch_eloc_wide_pairs(c, wk.nb_spins, total, wk.nb_parent, wk.partial, st));
+      if (e == hipSuccess && total > 0)
+        e = NQS_RUN(c, K_HOP3, st,
+                    launch_pathsum_finish(c, wk.nb_spins, total, wk.partial, wk.nb_lp, st));
+      if (e == hipSuccess)
+        e = NQS_RUN(c, K_HOP3, st,
+                    launch_hop_combine(c, sp, n, wk.nb_off, lp, e12, 4, wk.nb_lp, nullptr, 0,
+                                       e12 + 2, 4, st, 1));
+    } else {
+      if (e == hipSuccess && total > 0)
+        e = eloc_fused_any(c, wk.nb_spins, total, wk.partial, wk.nb_lp, wk.nb_e1e2, 4, st);
+      if (e == hipSuccess)
+        e = NQS_RUN(c, K_HOP3, st,
+                    launch_hop_combine(c, sp, n, wk.nb_off, lp, e12, 4, wk.nb_lp, wk.nb_e1e2, 4,
+                                       e12 + 2, 4, st));
+    }
   }
   for (int64_t s0 = 0; !composed_moments(c, NQS_OP_MOMENTS) && s0 < S && e == hipSuccess;
        s0 += wk.chunk) {

@@ -23,6 +23,7 @@
 // in the same format as the fused kernel, combined by its finish kernel.
 // Bonds beyond 4 kWideBonds per sample are handled in further passes.
 #include "theta_common.h"
+#include "hops.h"
 
 namespace nqs {
 
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
     const int32_t* __restrict__ bonds, const int32_t* __restrict__ wmap,
     const int32_t* __restrict__ wrow,
     const double* __restrict__ chi, const float* __restrict__ Tpm, const float* __restrict__ F,
-    double* __restrict__ part) {
+    double* __restrict__ part, const int16_t* __restrict__ parent) {
   using T = ThetaTraits<PREC>;
   using Cfg = WideCfg<N>;
   constexpr int NB = Cfg::NB, NK = nk_of<N, PREC>(), NSTG = Cfg::NSTG;
@@ -109,18 +110,29 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
     const int8_t* srow = spins + s * N;
     __syncthreads();                           // previous sample done with the list
     if (wv == 0) {
+      // with a parent bond b1 (s is the exchange neighbour s0^{b1} of a
+      // two-hop sum): the unordered-pair list of the second hops (b1 itself
+      // excluded, bonds disjoint from b1 only above it, counted twice: flag 0x4000)
+      const int b1 = parent ? (int)parent[s] : -1;
+      const int i1 = b1 >= 0 ? bonds[2 * b1] : -1, j1 = b1 >= 0 ? bonds[2 * b1 + 1] : -1;
       int n = 0;
       for (int base = 0; base < NB; base += 64) {
         const int b = base + lane;
-        bool anti = false;
+        bool anti = false, twice = false;
         int sp = 0;
         if (b < NB) {
-          sp = srow[bonds[2 * b]];
-          anti = sp != srow[bonds[2 * b + 1]];
+          const int bi = bonds[2 * b], bj = bonds[2 * b + 1];
+          sp = srow[bi];
+          anti = sp != srow[bj];
+          if (anti && b1 >= 0) {
+            const bool shared = bi == i1 || bi == j1 || bj == i1 || bj == j1;
+            anti = b != b1 && (shared || b > b1);
+            twice = !shared;
+          }
         }
         const unsigned long long msk = __ballot(anti);
         const int pos = __popcll(msk & ((1ull << lane) - 1ull));
-        if (anti) list[n + pos] = (uint16_t)(b | (sp > 0 ? 0x8000 : 0));
+        if (anti) list[n + pos] = (uint16_t)(b | (sp > 0 ? 0x8000 : 0) | (twice ? 0x4000 : 0));
         n += __popcll(msk);
       }
       if (lane == 0) nc_s = n;
@@ -142,13 +154,15 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
       for (int pass = 0; pass < npass; ++pass) {
         // this lane's bonds: list entries pass * 4 kWideBonds + q + 4 jb
         int offs[kWideBonds];                  // 2 * (row offset in floats) + (sign < 0)
+        double wt[kWideBonds];                 // 2 for an unordered pair counted twice
         const int i0 = pass * 4 * kWideBonds + q;
         const int nv = nc > i0 ? min(kWideBonds, (nc - i0 + 3) / 4) : 0;
 #pragma unroll
         for (int jb = 0; jb < kWideBonds; ++jb) {
           const int ii = i0 + 4 * jb;
           const int e = ii < nc ? list[ii] : 0;   // padding entries use bond 0
-          offs[jb] = wmap[(size_t)g * NB + (e & 0x7fff)] ^ (e >> 15);
+          offs[jb] = wmap[(size_t)g * NB + (e & 0x3fff)] ^ (e >> 15);
+          wt[jb] = (e & 0x4000) ? 2.0 : 1.0;
         }
         float Pr[kWideBonds], Pi[kWideBonds];
         float lpr = 1.f, lpi = 0.f;
@@ -266,8 +280,8 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
             double sr = 0.0, si = 0.0;
 #pragma unroll
             for (int jb = 0; jb < kWideBonds; ++jb) {
-              sr += jb < nv ? (double)Pr[jb] : 0.0;
-              si += jb < nv ? (double)Pi[jb] : 0.0;
+              sr += jb < nv ? wt[jb] * (double)Pr[jb] : 0.0;
+              si += jb < nv ? wt[jb] * (double)Pi[jb] : 0.0;
             }
             Qr += (double)ur * sr - (double)ui * si;
             Qi += (double)ur * si + (double)ui * sr;
@@ -304,14 +318,15 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
 #undef NQS_STAGE_STORE
 
 template <int N, int PREC>
-hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, hipStream_t st) {
+hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, hipStream_t st,
+               const int16_t* parent = nullptr) {
   const int64_t blocks = std::min<int64_t>(S, c->n_cu > 0 ? c->n_cu : 256);
   eloc_wide_kernel<N, PREC><<<(unsigned)blocks, 64 * kWideWaves, 0, st>>>(
       spins, S, c->dev.perm, c->G, c->K, c->M,
       (const typename ThetaTraits<PREC>::AFrag*)c->par.wfrag, (const float*)c->par.bias,
       (const float*)c->par.avec, c->dev.bonds, c->dev.wmap, c->dev.wrow, c->dev.chi,
       (const float*)c->par.Tpm,
-      (const float*)c->par.F, part);
+      (const float*)c->par.F, part, parent);
   return hipGetLastError();
 }
 
@@ -324,12 +339,20 @@ bool eloc_wide_supported(const nqs_ctx* c) {
 
 hipError_t launch_eloc_wide(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part,
                             hipStream_t st) {
+  return launch_eloc_wide_pairs(c, spins, S, nullptr, part, st);
+}
+
+hipError_t launch_eloc_wide_pairs(const nqs_ctx* c, const int8_t* spins, int64_t S,
+                                  const int16_t* parent, double* part, hipStream_t st) {
   if (S <= 0) return hipSuccess;
   const bool bf = c->prec == NQS_BF16X2;
   switch (c->N) {
-    case 36: return bf ? run<36, NQS_BF16X2>(c, spins, S, part, st) : run<36, NQS_FP32>(c, spins, S, part, st);
-    case 64: return bf ? run<64, NQS_BF16X2>(c, spins, S, part, st) : run<64, NQS_FP32>(c, spins, S, part, st);
-    case 100: return bf ? run<100, NQS_BF16X2>(c, spins, S, part, st) : run<100, NQS_FP32>(c, spins, S, part, st);
+    case 36: return bf ? run<36, NQS_BF16X2>(c, spins, S, part, st, parent)
+                       : run<36, NQS_FP32>(c, spins, S, part, st, parent);
+    case 64: return bf ? run<64, NQS_BF16X2>(c, spins, S, part, st, parent)
+                       : run<64, NQS_FP32>(c, spins, S, part, st, parent);
+    case 100: return bf ? run<100, NQS_BF16X2>(c, spins, S, part, st, parent)
+                        : run<100, NQS_FP32>(c, spins, S, part, st, parent);
     default: return hipErrorNotSupported;
   }
 }

@@ -68,7 +68,8 @@ __global__ __launch_bounds__(64 * kNbWaves) void nb_write_kernel(const int8_t* _
                                                                  int64_t n, int N, int NB,
                                                                  const int32_t* __restrict__ bonds,
                                                                  const int32_t* __restrict__ off,
-                                                                 int8_t* __restrict__ out) {
+                                                                 int8_t* __restrict__ out,
+                                                                 int16_t* __restrict__ parent) {
   const int64_t s = (int64_t)blockIdx.x * kNbWaves + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (s >= n) return;
@@ -85,6 +86,7 @@ __global__ __launch_bounds__(64 * kNbWaves) void nb_write_kernel(const int8_t* _
       for (int x = 0; x < N; ++x) row[x] = srow[x];
       row[i] = srow[j];
       row[j] = srow[i];
+      if (parent) parent[k] = (int16_t)b;
     }
     pos += __popcll(m);
   }
@@ -97,13 +99,13 @@ __global__ __launch_bounds__(64 * kNbWaves) void hop_combine_kernel(
     const double* __restrict__ bond_J, const int32_t* __restrict__ off,
     const double* __restrict__ lp, const double* __restrict__ eprev, int eprev_stride,
     const double* __restrict__ lp_nb, const double* __restrict__ enb, int enb_stride,
-    double* __restrict__ out, int out_stride) {
+    double* __restrict__ out, int out_stride, int back) {
   const int64_t s = (int64_t)blockIdx.x * kNbWaves + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (s >= n) return;
   const int8_t* srow = spins + s * N;
   const double lr = lp[2 * s], li = lp[2 * s + 1];
-  double diag = 0.0, ar = 0.0, ai = 0.0;
+  double diag = 0.0, ar = 0.0, ai = 0.0, jj = 0.0;
   int64_t pos = off[s];
   for (int base = 0; base < NB; base += 64) {
     const int b = base + lane;
@@ -112,6 +114,7 @@ __global__ __launch_bounds__(64 * kNbWaves) void hop_combine_kernel(
       const int si = srow[bonds[2 * b]], sj = srow[bonds[2 * b + 1]];
       diag += 0.25 * bond_J[b] * (double)(si * sj);
       anti = si != sj;
+      if (anti) jj += 0.25 * bond_J[b] * bond_J[b];
     }
     const unsigned long long m = __ballot(anti);
     if (anti) {
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(64 * kNbWaves) void hop_combine_kernel(
       if (mag != 0.0) {
         double sn, cs;
         sincos(lp_nb[2 * k + 1] - li, &sn, &cs);
-        const double fr = enb[enb_stride * k], fi = enb[enb_stride * k + 1];
+        const double fr = enb ? enb[enb_stride * k] : 1.0, fi = enb ? enb[enb_stride * k + 1] : 0.0;
         ar += mag * (cs * fr - sn * fi);
         ai += mag * (cs * fi + sn * fr);
       }
@@ -133,9 +136,42 @@ __global__ __launch_bounds__(64 * kNbWaves) void hop_combine_kernel(
   diag = wave_sum(diag);
   ar = wave_sum(ar);
   ai = wave_sum(ai);
+  jj = back ? wave_sum(jj) : 0.0;
   if (lane == 0) {
-    out[out_stride * s] = diag * eprev[eprev_stride * s] + ar;
+    out[out_stride * s] = diag * eprev[eprev_stride * s] + ar + jj;
     out[out_stride * s + 1] = diag * eprev[eprev_stride * s + 1] + ai;
+  }
+}
+
+// Path sums from the E_loc kernels' partials [S][G/16][6] = (m, den, Q, -):
+// log(e^M sum_blocks e^{m - M} (H_ss den + Q)), i.e. log of
+// sum_g chi_g psi_s(g s) (H_ss + sum_b (J_b/2) R_gb) without the division by
+// psi(s) that E_loc makes (finite where psi(s) vanishes).
+__global__ __launch_bounds__(64) void pathsum_finish_kernel(
+    const int8_t* __restrict__ spins, int N, int NB, int cbs, const int32_t* __restrict__ bonds,
+    const double* __restrict__ bond_J, const double* __restrict__ part, double* __restrict__ out) {
+  const int64_t s = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int8_t* srow = spins + s * N;
+  double d = 0.0;
+  for (int b = lane; b < NB; b += 64)
+    d += 0.25 * bond_J[b] * (double)(srow[bonds[2 * b]] * srow[bonds[2 * b + 1]]);
+  d = wave_sum(d);
+  const double* ps = part + (size_t)s * cbs * 6;
+  double mx = -INFINITY;
+  for (int i = lane; i < cbs; i += 64) mx = fmax(mx, ps[6 * i]);
+  mx = wave_max(mx);
+  double ar = 0.0, ai = 0.0;
+  for (int i = lane; i < cbs; i += 64) {
+    const double e = exp(ps[6 * i] - mx);
+    ar += e * (d * ps[6 * i + 1] + ps[6 * i + 3]);
+    ai += e * (d * ps[6 * i + 2] + ps[6 * i + 4]);
+  }
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  if (lane == 0) {
+    out[2 * s] = mx + 0.5 * log(ar * ar + ai * ai);
+    out[2 * s + 1] = atan2(ai, ar);
   }
 }
 
@@ -296,18 +332,35 @@ hipError_t launch_nb_write(const nqs_ctx* c, const int8_t* spins, int64_t n, con
                            int8_t* out, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   nb_write_kernel<<<nb_blocks(n), 64 * kNbWaves, 0, st>>>(spins, n, c->N, c->NB, c->dev.bonds, off,
-                                                          out);
+                                                          out, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_nb_write_parent(const nqs_ctx* c, const int8_t* spins, int64_t n,
+                                  const int32_t* off, int8_t* out, int16_t* parent,
+                                  hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  nb_write_kernel<<<nb_blocks(n), 64 * kNbWaves, 0, st>>>(spins, n, c->N, c->NB, c->dev.bonds, off,
+                                                          out, parent);
+  return hipGetLastError();
+}
+
+hipError_t launch_pathsum_finish(const nqs_ctx* c, const int8_t* spins, int64_t S,
+                                 const double* part, double* out, hipStream_t st) {
+  if (S <= 0) return hipSuccess;
+  pathsum_finish_kernel<<<(unsigned)S, 64, 0, st>>>(spins, c->N, c->NB, c->G / 16, c->dev.bonds,
+                                                    c->dev.bond_J, part, out);
   return hipGetLastError();
 }
 
 hipError_t launch_hop_combine(const nqs_ctx* c, const int8_t* spins, int64_t n, const int32_t* off,
                               const double* lp, const double* eprev, int eprev_stride,
                               const double* lp_nb, const double* enb, int enb_stride, double* out,
-                              int out_stride, hipStream_t st) {
+                              int out_stride, hipStream_t st, int back) {
   if (n <= 0) return hipSuccess;
   hop_combine_kernel<<<nb_blocks(n), 64 * kNbWaves, 0, st>>>(
       spins, n, c->N, c->NB, c->dev.bonds, c->dev.bond_J, off, lp, eprev, eprev_stride, lp_nb, enb,
-      enb_stride, out, out_stride);
+      enb_stride, out, out_stride, back);
   return hipGetLastError();
 }
 

@@ -291,3 +291,18 @@ def test_p2_full_size_bench_launch():
         e3 = diag * e123[r, 1] + (0.5 * J[anti] * np.exp(lpn - lp0[r]) * e2n).sum()
         assert abs(e123[r, 2] - e3) <= TOL["fp32"] * max(1.0, abs(e3)), (r, e123[r, 2], e3)
     assert not res["degenerate"] and res["e_p2"] <= res["e_p1"] <= res["h1"]
+
+
+def test_wide_model_e2_pair_lists_fp32():
+    """6x6 with 136 hidden units (the wide E_loc kernel): e2 from the exchange
+    neighbours run through the wide kernel with their parents' unordered-pair
+    bond lists, combined as path sums, against the oracle's direct e2."""
+    w = dataclasses.replace(WORKLOADS["6x6_fp32_lanczos"], n_hidden=136)
+    p = stress_params(w, 0.05, 13)
+    om = oracle.Model.from_workload(w)
+    sp = random_sz0_spins(w.N, 2, 41)
+    m = make(w, p)
+    res, e12 = m.lanczos_moments(cuda(sp), exact=False)
+    e12 = e12.cpu().numpy()
+    assert max_rel_err(e12[:, 0], oracle.eloc_direct(om, p, sp)) < TOL["fp32"]
+    assert max_rel_err(e12[:, 1], oracle.e2_direct(om, p, sp)) < TOL["fp32"]
