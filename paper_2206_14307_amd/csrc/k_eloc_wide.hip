@@ -45,7 +45,9 @@ struct WideCfg {
                                 NB * 4 + 16;
 };
 
-template <int N, int PREC>
+// PAIRS: the rows are exchange neighbours with parent bonds (parent[s]); the
+// bond list is the parent's unordered-pair list and pairs counted twice weigh 2.
+template <int N, int PREC, bool PAIRS>
 __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
     const int8_t* __restrict__ spins, int64_t S, const uint8_t* __restrict__ perm, int G, int K,
     int M, const typename ThetaTraits<PREC>::AFrag* __restrict__ wfrag,
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
       // with a parent bond b1 (s is the exchange neighbour s0^{b1} of a
       // two-hop sum): the unordered-pair list of the second hops (b1 itself
       // excluded, bonds disjoint from b1 only above it, counted twice: flag 0x4000)
-      const int b1 = parent ? (int)parent[s] : -1;
+      const int b1 = PAIRS ? (int)parent[s] : -1;
       const int i1 = b1 >= 0 ? bonds[2 * b1] : -1, j1 = b1 >= 0 ? bonds[2 * b1 + 1] : -1;
       int n = 0;
       for (int base = 0; base < NB; base += 64) {
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
       for (int pass = 0; pass < npass; ++pass) {
         // this lane's bonds: list entries pass * 4 kWideBonds + q + 4 jb
         int offs[kWideBonds];                  // 2 * (row offset in floats) + (sign < 0)
-        double wt[kWideBonds];                 // 2 for an unordered pair counted twice
+        uint32_t twice = 0u;                   // bit jb: an unordered pair counted twice
         const int i0 = pass * 4 * kWideBonds + q;
         const int nv = nc > i0 ? min(kWideBonds, (nc - i0 + 3) / 4) : 0;
 #pragma unroll
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
           const int ii = i0 + 4 * jb;
           const int e = ii < nc ? list[ii] : 0;   // padding entries use bond 0
           offs[jb] = wmap[(size_t)g * NB + (e & 0x3fff)] ^ (e >> 15);
-          wt[jb] = (e & 0x4000) ? 2.0 : 1.0;
+          if (PAIRS && (e & 0x4000)) twice |= 1u << jb;
         }
         float Pr[kWideBonds], Pi[kWideBonds];
         float lpr = 1.f, lpi = 0.f;
@@ -280,8 +282,14 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
             double sr = 0.0, si = 0.0;
 #pragma unroll
             for (int jb = 0; jb < kWideBonds; ++jb) {
-              sr += jb < nv ? wt[jb] * (double)Pr[jb] : 0.0;
-              si += jb < nv ? wt[jb] * (double)Pi[jb] : 0.0;
+              if constexpr (PAIRS) {
+                const double wj = ((twice >> jb) & 1u) ? 2.0 : 1.0;
+                sr += jb < nv ? wj * (double)Pr[jb] : 0.0;
+                si += jb < nv ? wj * (double)Pi[jb] : 0.0;
+              } else {
+                sr += jb < nv ? (double)Pr[jb] : 0.0;
+                si += jb < nv ? (double)Pi[jb] : 0.0;
+              }
             }
             Qr += (double)ur * sr - (double)ui * si;
             Qi += (double)ur * si + (double)ui * sr;
@@ -321,12 +329,17 @@ template <int N, int PREC>
 hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, hipStream_t st,
                const int16_t* parent = nullptr) {
   const int64_t blocks = std::min<int64_t>(S, c->n_cu > 0 ? c->n_cu : 256);
-  eloc_wide_kernel<N, PREC><<<(unsigned)blocks, 64 * kWideWaves, 0, st>>>(
-      spins, S, c->dev.perm, c->G, c->K, c->M,
-      (const typename ThetaTraits<PREC>::AFrag*)c->par.wfrag, (const float*)c->par.bias,
-      (const float*)c->par.avec, c->dev.bonds, c->dev.wmap, c->dev.wrow, c->dev.chi,
-      (const float*)c->par.Tpm,
-      (const float*)c->par.F, part, parent);
+  const auto* wf = (const typename ThetaTraits<PREC>::AFrag*)c->par.wfrag;
+  if (parent)
+    eloc_wide_kernel<N, PREC, true><<<(unsigned)blocks, 64 * kWideWaves, 0, st>>>(
+        spins, S, c->dev.perm, c->G, c->K, c->M, wf, (const float*)c->par.bias,
+        (const float*)c->par.avec, c->dev.bonds, c->dev.wmap, c->dev.wrow, c->dev.chi,
+        (const float*)c->par.Tpm, (const float*)c->par.F, part, parent);
+  else
+    eloc_wide_kernel<N, PREC, false><<<(unsigned)blocks, 64 * kWideWaves, 0, st>>>(
+        spins, S, c->dev.perm, c->G, c->K, c->M, wf, (const float*)c->par.bias,
+        (const float*)c->par.avec, c->dev.bonds, c->dev.wmap, c->dev.wrow, c->dev.chi,
+        (const float*)c->par.Tpm, (const float*)c->par.F, part, nullptr);
   return hipGetLastError();
 }
 
