@@ -157,8 +157,10 @@ nqs_status nqs_eloc(nqs_ctx* ctx, const int8_t* spins, int64_t S, double* logpsi
  * (Sec. 3.3).  For models without the register-resident two-hop kernel
  * (K > 1, or K*M beyond its compiled sizes) e2 is formed as
  * H_ss e1 + sum_b (J_b/2) psi(s^b)/psi(s) E_loc(s^b) from the fused / wide
- * E_loc kernels run on the exchange neighbours, which synchronises once per
- * chunk of configurations.  exact = 0: uniform weights (Monte-Carlo samples);
+ * E_loc kernels run on the exchange neighbours (the wide kernel on each
+ * neighbour's unordered-pair second-hop list, as path sums, with the
+ * exchanges there and back added in closed form), which synchronises once
+ * per chunk of configurations.  exact = 0: uniform weights (Monte-Carlo samples);
  * exact = 1: Born weights |psi|^2 / sum |psi|^2 (Sec. 3.2, Eq. (9)) over the
  * given configurations (the whole Sz = 0 sector for exact results).
  * e1e2_out (complex [S][2]) is optional.  Writes *out and synchronises the
