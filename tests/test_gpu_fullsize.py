@@ -5,6 +5,9 @@ configuration, seconds per row at 8x8 and 10x10).
 
 * 6x6 Lanczos workload, 8192 configurations: e1 and e2 of nqs_lanczos_moments;
 * 8x8 K = 4 x M = 256, 16 384 configurations: nqs_eloc with FP32 and split-BF16 theta;
+  nqs_lanczos_moments (split BF16): sampled rows equal a separate call on those rows
+  alone bit for bit, and e2 = H_ss e1 + sum_b (J_b/2) psi(s^b)/psi(s) E_loc(s^b) with
+  nqs_logpsi / nqs_eloc on one row's exchange neighbours (E_loc oracle-checked above);
 * 10x10 M = 400, 32 768 configurations: nqs_eloc, nqs_grad and nqs_logpsi (split BF16).
 """
 import dataclasses
@@ -69,3 +72,26 @@ def test_eloc_grad_logpsi_10x10_full_size():
     Os = O[torch.from_numpy(rows).cuda()].cpu().numpy()
     del O
     assert max_row_rel_err(Os, oracle.logderiv(om, p, sp[rows])) < tol
+
+
+def test_lanczos_moments_8x8_full_size():
+    w, p, m, sp, rows, om = _setup("8x8_k4_m256")
+    res, e12 = m.lanczos_moments(torch.from_numpy(sp).cuda(), exact=False)
+    e12 = e12.cpu().numpy()
+    assert res["n"] == len(sp) and np.isfinite(res["e_p1"])
+    _, e12s = m.lanczos_moments(torch.from_numpy(np.ascontiguousarray(sp[rows])).cuda(), exact=False)
+    assert np.array_equal(e12[rows], e12s.cpu().numpy())
+    bonds, J = om.lat.bonds, np.asarray(om.bond_J, np.float64)
+    r = int(rows[0])
+    s = sp[r]
+    anti = np.nonzero(s[bonds[:, 0]] != s[bonds[:, 1]])[0]
+    nb = np.repeat(s[None, :], len(anti), axis=0)
+    for k, b in enumerate(anti):
+        i, j = bonds[b]
+        nb[k, i], nb[k, j] = s[j], s[i]
+    lp0 = m.logpsi(torch.from_numpy(s[None, :].copy()).cuda()).cpu().numpy()[0]
+    lpn, eln = m.eloc(torch.from_numpy(nb).cuda())
+    lpn, eln = lpn.cpu().numpy(), eln.cpu().numpy()
+    diag = 0.25 * float((J * s[bonds[:, 0]] * s[bonds[:, 1]]).sum())
+    e2 = diag * e12[r, 0] + (0.5 * J[anti] * np.exp(lpn - lp0) * eln).sum()
+    assert abs(e12[r, 1] - e2) <= TOL[w.precision] * max(1.0, abs(e2)), (e12[r, 1], e2)
