@@ -12,8 +12,8 @@
 //     as four real products, lower block triangle only, stored in FP64;
 //  3. blocked right-looking FP64 Cholesky T = L L^H with 32 x 32 blocks:
 //     diagonal factorisation in LDS, panel triangular solve, Hermitian
-//     updates on FP64 MFMA (within a panel of 4 block columns per column,
-//     then one rank-128 update of the trailing matrix per panel);
+//     updates on FP64 MFMA (within a panel of 8 block columns per column,
+//     then one rank-256 update of the trailing matrix per panel);
 //  4. L y = eps, L^H x = y, dtheta = -dtau O_bar^H x.
 // S is padded to a multiple of 32 with zero rows (their T block is lambda I
 // and their eps is 0, so they drop out of x and dtheta).
@@ -29,7 +29,7 @@ namespace nqs {
 namespace {
 
 constexpr int kB = 32;   // Cholesky / Gram block
-constexpr int kPanel = 4; // block columns per Cholesky panel (one trailing update each)
+constexpr int kPanel = 8;  // block columns per Cholesky panel (one trailing update each)
 
 __device__ __forceinline__ f64x4 mma(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
