@@ -436,12 +436,14 @@ def leg_vmc(steps=3):
                  n_per_chain=8, dtau=0.05)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    res, _ = m4.lanczos_moments(m4.enumerate_sz0(), exact=True)
-    e0 = -0.701780 * w4.N          # 4x4 Heisenberg ground state (exact diagonalisation)
+    res, _ = m4.lanczos_moments_p2(m4.enumerate_sz0(), exact=True, want_e123=False)
+    e0 = -0.701780 * w4.N          # 4x4 Heisenberg ground state (exact diagonalisation, 6 digits)
     out["train_4x4_j2_0"] = {"steps": len(hist), "seconds": t_train,
-                             "exact_energy": res["h1"], "e_p1": res["e_p1"], "e0_ed": e0,
+                             "exact_energy": res["h1"], "e_p1": res["e_p1"], "e_p2": res["e_p2"],
+                             "e0_ed_6_digits": e0,
                              "rel_err": abs(res["h1"] - e0) / abs(e0),
-                             "rel_err_p1": abs(res["e_p1"] - e0) / abs(e0)}
+                             "rel_err_p1": abs(res["e_p1"] - e0) / abs(e0),
+                             "e_p1_minus_e_p2": res["e_p1"] - res["e_p2"]}
     return out
 
 

@@ -80,15 +80,17 @@ def test_training_4x4_reaches_exact_energy(J2, steps, gate, solver):
     lattice (256 chains x 8 samples per step, dtau = 0.05, lambda = 1e-6):
     the exact energy of the trained state (the whole Sz = 0 sector with Born
     weights) is within `gate` of the exact-diagonalisation ground state, and
-    the p = 1 Lanczos energy is lower still (Sec. 3.3)."""
+    the p = 1 and p = 2 Lanczos energies are lower still (Sec. 3.3)."""
     from paper_2206_14307_amd.vmc import train
     w = dataclasses.replace(WORKLOADS["4x4_fp64_exact"], is_complex=True, J2=J2)
     m = make(w, draw_params(w))
     init = torch.from_numpy(random_sz0_spins(w.N, 256, 3)).cuda()
     hist = train(m, init, steps=steps, n_per_chain=8, dtau=0.05, solver=solver)
     assert len(hist) == steps and hist[-1]["energy"] < hist[0]["energy"]
-    res, _ = m.lanczos_moments(m.enumerate_sz0(), exact=True)
+    res, _ = m.lanczos_moments_p2(m.enumerate_sz0(), exact=True, want_e123=False)
     e0 = oracle.ground_state(oracle.Model.from_workload(w))[0][0]
     assert res["h1"] >= e0 - 1e-9                    # variational bound
     assert abs(res["h1"] - e0) < gate * abs(e0)
     assert e0 - 1e-9 <= res["e_p1"] <= res["h1"]
+    # p = 2 (Eq. (19)): lower again, still above the ground state
+    assert e0 - 1e-9 <= res["e_p2"] <= res["e_p1"] + 1e-12 * abs(e0)
