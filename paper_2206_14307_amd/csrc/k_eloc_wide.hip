@@ -159,6 +159,11 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
         uint32_t twice = 0u;                   // bit jb: an unordered pair counted twice
         const int i0 = pass * 4 * kWideBonds + q;
         const int nv = nc > i0 ? min(kWideBonds, (nc - i0 + 3) / 4) : 0;
+        // bonds per lane of lane group 0 (the most of any group): a partly
+        // filled pass skips the empty pairs of slots
+        const int p0 = pass * 4 * kWideBonds;
+        const int nvu = __builtin_amdgcn_readfirstlane(
+            nc > p0 ? min(kWideBonds, (nc - p0 + 3) / 4) : 0);
 #pragma unroll
         for (int jb = 0; jb < kWideBonds; ++jb) {
           const int ii = i0 + 4 * jb;
@@ -217,6 +222,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
           // bond products of the chunk, two bonds at a time
 #pragma unroll
           for (int jb = 0; jb < kWideBonds; jb += 2) {
+            if (jb < nvu) {
             const float* r0 = Tc[buf] + (offs[jb] >> 1);
             const float* r1 = Tc[buf] + (offs[jb + 1] >> 1);
             const float sg0 = (offs[jb] & 1) ? -1.f : 1.f, sg1 = (offs[jb + 1] & 1) ? -1.f : 1.f;
@@ -242,6 +248,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
               }
             }
             Pr[jb] = ar; Pi[jb] = ai; Pr[jb + 1] = br; Pi[jb + 1] = bi;
+            }
           }
           if (ch % CPR == CPR - 1) {           // RBM k complete: weight and sum
             apply_parity(lpr, lpi, lpar);
