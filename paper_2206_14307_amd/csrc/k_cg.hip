@@ -25,7 +25,7 @@ namespace nqs {
 namespace {
 
 constexpr int kCgRows = 16;      // rows per block of the row GEMV
-constexpr int kRowParts = 8;     // column parts of the complex64 row GEMV
+constexpr int kRowParts = 8;     // most column parts of the complex64 row GEMV
 constexpr int kCgThreads = 256;
 constexpr int kVecThreads = 1024;
 
@@ -119,16 +119,17 @@ __global__ __launch_bounds__(kCgThreads) void cols_kernel(const RO* __restrict__
 
 // complex64 O: every P here is even (N even, M a multiple of 8), so a row's
 // column pairs are 16-byte aligned and one float4 load brings two columns.
-// Block (x, y) takes rows x kCgRows .. and column part y of kRowParts and
-// writes its raw partial sums upart[y][s]: many more blocks than the device
-// holds at once, so the last round of blocks is a small part of the pass.
+// Block (x, y) takes rows x kCgRows .. and column part y of gridDim.y (at
+// most kRowParts) and writes its raw partial sums upart[y][s]: many more
+// blocks than the device holds at once, so the last round of blocks is a
+// small part of the pass.
 __global__ __launch_bounds__(kCgThreads) void rows2_kernel(const float* __restrict__ O, int64_t S,
                                                            int64_t P, const double* __restrict__ v,
                                                            double* __restrict__ upart) {
   __shared__ double red[kCgRows][2][kCgThreads / 64];
   const int64_t s0 = (int64_t)blockIdx.x * kCgRows;
   const int64_t P2 = P / 2;
-  const int64_t span = (P2 + kRowParts - 1) / kRowParts;
+  const int64_t span = (P2 + gridDim.y - 1) / gridDim.y;
   const int64_t kb = (int64_t)blockIdx.y * span, ke = std::min<int64_t>(P2, kb + span);
   double ar[kCgRows], ai[kCgRows];
 #pragma unroll
@@ -172,15 +173,14 @@ __global__ __launch_bounds__(kCgThreads) void rows2_kernel(const float* __restri
 
 // u[s] = (sum over the column parts in a fixed order - m . v) / sqrt(S)
 __global__ __launch_bounds__(kCgThreads) void rows2_finish_kernel(const double* __restrict__ upart,
-                                                                  int64_t S,
+                                                                  int parts, int64_t S,
                                                                   const double* __restrict__ mv,
                                                                   double inv_sqrt_s,
                                                                   double* __restrict__ u) {
   const int64_t s = (int64_t)blockIdx.x * kCgThreads + threadIdx.x;
   if (s >= S) return;
   double sr = 0.0, si = 0.0;
-#pragma unroll
-  for (int y = 0; y < kRowParts; ++y) {
+  for (int y = 0; y < parts; ++y) {
     sr += upart[2 * ((size_t)y * S + s)];
     si += upart[2 * ((size_t)y * S + s) + 1];
   }
@@ -489,10 +489,13 @@ hipError_t cg_run(nqs_ctx* c, const RO* O, const double* eloc, int64_t S, double
     // q = A p
     mdot_kernel<<<1, kVecThreads, 0, st>>>(m, p, P, scal);
     if constexpr (sizeof(RO) == 4) {
-      const dim3 rgrid((unsigned)((S + kCgRows - 1) / kCgRows), (unsigned)kRowParts);
+      // column parts of at least four sweeps of the block over column pairs
+      const int parts = (int)std::max<int64_t>(
+          1, std::min<int64_t>(kRowParts, P / 2 / (4 * kCgThreads)));
+      const dim3 rgrid((unsigned)((S + kCgRows - 1) / kCgRows), (unsigned)parts);
       rows2_kernel<<<rgrid, kCgThreads, 0, st>>>(O, S, P, p, upart);
       rows2_finish_kernel<<<(unsigned)((S + kCgThreads - 1) / kCgThreads), kCgThreads, 0, st>>>(
-          upart, S, scal, is, u);
+          upart, parts, S, scal, is, u);
     } else
       rows_kernel<RO><<<(unsigned)((S + kCgRows - 1) / kCgRows), kCgThreads, 0, st>>>(O, S, P, p,
                                                                                    scal, is, u);
