@@ -16,12 +16,12 @@
 //   * tanh(theta) of the chunk goes through a small LDS tile so that lane
 //     (qg, c) holds all kHC values of image c, and the lane multiplies the
 //     running products F_s prod_h (s + t_h T_h) of its bonds b = qg + 4 jb
-//     (jb < kWideBonds) of the list, the bond rows read from LDS.
+//     (jb < wide_bonds) of the list, the bond rows read from LDS.
 // At the end of each RBM the products are weighted with the image weights
 // u = chi e^{L - m} (m a running maximum over the RBMs of the wave's images)
 // and summed; the wave emits (m, sum u, sum u R) per (sample, column block)
 // in the same format as the fused kernel, combined by its finish kernel.
-// Bonds beyond 4 kWideBonds per sample are handled in further passes.
+// Bonds beyond 4 wide_bonds per sample are handled in further passes.
 #include "theta_common.h"
 #include "hops.h"
 
@@ -30,7 +30,14 @@ namespace nqs {
 namespace {
 
 constexpr int kWideWaves = 8;
-constexpr int kWideBonds = 16;     // bonds per lane and pass
+// bonds per lane and pass (even: the products run two bonds at a time).
+// Each pass recomputes theta, so 72 bonds per pass at 8x8 and 10x10 take
+// their ~130 and ~200 antiparallel bonds in 2 and 3 passes where 64 took 3
+// and 4 (10-11 % faster, with somewhat more spilling at N = 100).  The
+// unordered-pair lists at 10x10 (~100 entries) take 2 passes either way, and
+// there the extra registers only spill.
+template <int N, bool PAIRS>
+constexpr int wide_bonds() { return N >= 64 && !(PAIRS && N >= 100) ? 18 : 16; }
 constexpr int kHC = 8;             // hidden units per chunk (multiple of 8)
 constexpr int kRP = kHC / 2;       // float4 per staged row
 constexpr int kTS = 2 * kHC + 4;   // LDS row stride of the staged table (floats)
@@ -59,6 +66,8 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
   using T = ThetaTraits<PREC>;
   using Cfg = WideCfg<N>;
   constexpr int NB = Cfg::NB, NK = nk_of<N, PREC>(), NSTG = Cfg::NSTG;
+  constexpr int kWB = wide_bonds<N, PAIRS>();
+  static_assert(kWB % 2 == 0 && kWB <= 32, "bond slots: pairs, one bit each in a word");
   static_assert(kTS == 4 * kWideRow16, "row size of the placement");
   __shared__ __align__(16) float Tc[2][Cfg::CAP16 * 4];
   __shared__ int wrl[NB];                    // row starts in floats
@@ -141,7 +150,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
     }
     __syncthreads();
     const int nc = nc_s;
-    const int npass = nc > 0 ? (nc + 4 * kWideBonds - 1) / (4 * kWideBonds) : 1;
+    const int npass = nc > 0 ? (nc + 4 * kWB - 1) / (4 * kWB) : 1;
 
     for (int rd = 0; rd < rounds; ++rd) {
       const int blk = rd * kWideWaves + wv;
@@ -154,24 +163,24 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
       double m_item = -INFINITY, Qr = 0.0, Qi = 0.0, denr = 0.0, deni = 0.0;
 
       for (int pass = 0; pass < npass; ++pass) {
-        // this lane's bonds: list entries pass * 4 kWideBonds + q + 4 jb
-        int offs[kWideBonds];                  // 2 * (row offset in floats) + (sign < 0)
+        // this lane's bonds: list entries pass * 4 kWB + q + 4 jb
+        int offs[kWB];                  // 2 * (row offset in floats) + (sign < 0)
         uint32_t twice = 0u;                   // bit jb: an unordered pair counted twice
-        const int i0 = pass * 4 * kWideBonds + q;
-        const int nv = nc > i0 ? min(kWideBonds, (nc - i0 + 3) / 4) : 0;
+        const int i0 = pass * 4 * kWB + q;
+        const int nv = nc > i0 ? min(kWB, (nc - i0 + 3) / 4) : 0;
         // bonds per lane of lane group 0 (the most of any group): a partly
         // filled pass skips the empty pairs of slots
-        const int p0 = pass * 4 * kWideBonds;
+        const int p0 = pass * 4 * kWB;
         const int nvu = __builtin_amdgcn_readfirstlane(
-            nc > p0 ? min(kWideBonds, (nc - p0 + 3) / 4) : 0);
+            nc > p0 ? min(kWB, (nc - p0 + 3) / 4) : 0);
 #pragma unroll
-        for (int jb = 0; jb < kWideBonds; ++jb) {
+        for (int jb = 0; jb < kWB; ++jb) {
           const int ii = i0 + 4 * jb;
           const int e = ii < nc ? list[ii] : 0;   // padding entries use bond 0
           offs[jb] = wmap[(size_t)g * NB + (e & 0x3fff)] ^ (e >> 15);
           if (PAIRS && (e & 0x4000)) twice |= 1u << jb;
         }
-        float Pr[kWideBonds], Pi[kWideBonds];
+        float Pr[kWB], Pi[kWB];
         float lpr = 1.f, lpi = 0.f;
         int lpe = 0;
         uint32_t lpar = 0u;
@@ -183,7 +192,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
           const int nxt = ch + 1 < NCH ? ch + 1 : 0;
           if (ch % CPR == 0) {                 // RBM start: products begin at F_s
 #pragma unroll
-            for (int jb = 0; jb < kWideBonds; ++jb) {
+            for (int jb = 0; jb < kWB; ++jb) {
               const float* f = Tc[buf] + (offs[jb] >> 1) + 2 * kHC + 2 * (offs[jb] & 1);
               Pr[jb] = f[0];
               Pi[jb] = f[1];
@@ -221,7 +230,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
           NQS_STAGE_LOAD(nxt)                  // lands during the bond products
           // bond products of the chunk, two bonds at a time
 #pragma unroll
-          for (int jb = 0; jb < kWideBonds; jb += 2) {
+          for (int jb = 0; jb < kWB; jb += 2) {
             if (jb < nvu) {
             const float* r0 = Tc[buf] + (offs[jb] >> 1);
             const float* r1 = Tc[buf] + (offs[jb + 1] >> 1);
@@ -288,7 +297,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
             const float ur = e * (pr * cs - pi * sn), ui = e * (pr * sn + pi * cs);
             double sr = 0.0, si = 0.0;
 #pragma unroll
-            for (int jb = 0; jb < kWideBonds; ++jb) {
+            for (int jb = 0; jb < kWB; ++jb) {
               if constexpr (PAIRS) {
                 const double wj = ((twice >> jb) & 1u) ? 2.0 : 1.0;
                 sr += jb < nv ? wj * (double)Pr[jb] : 0.0;
