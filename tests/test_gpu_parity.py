@@ -301,7 +301,7 @@ def _neel_and_stripe(L):
 ])
 def test_wide_models_many_samples_and_bond_passes(name, over, std):
     """Models with K*M > 128 take the wide kernel: one workgroup per sample,
-    hidden units in chunks, 16 bonds per lane and pass.  300 configurations
+    hidden units in chunks, 18 bonds per lane and pass (16 at N = 36).  300 configurations
     (more than one per workgroup) with the Neel and stripe states first (2N and
     3N antiparallel bonds: several bond passes); rows checked one by one."""
     w = dataclasses.replace(WORKLOADS[name], **over)
@@ -317,6 +317,62 @@ def test_wide_models_many_samples_and_bond_passes(name, over, std):
     tol = TOL[w.precision]
     assert max_logpsi_err(glp.cpu().numpy()[rows], oracle.logpsi(om, p, sub)) < tol
     assert max_rel_err(gel.cpu().numpy()[rows], oracle.eloc_direct(om, p, sub)) < tol
+
+
+def _anti_count(om, s):
+    """Antiparallel coupled bonds of configuration s."""
+    b = om.lat.bonds[om.bond_J != 0]
+    return int(np.sum(s[b[:, 0]] != s[b[:, 1]]))
+
+
+def _with_anti_count(om, target, seed):
+    """An Sz = 0 configuration with exactly `target` antiparallel coupled
+    bonds: random exchanges of an up and a down spin from a random start, kept
+    when they do not move the count away from the target."""
+    rng = np.random.default_rng(seed)
+    s = random_sz0_spins(om.N, 1, seed)[0].copy()
+    n = _anti_count(om, s)
+    for _ in range(50000):
+        if n == target:
+            return s
+        i = rng.choice(np.flatnonzero(s > 0))
+        j = rng.choice(np.flatnonzero(s < 0))
+        s[i], s[j] = s[j], s[i]
+        n2 = _anti_count(om, s)
+        if abs(n2 - target) <= abs(n - target):
+            n = n2
+        else:
+            s[i], s[j] = s[j], s[i]
+    raise AssertionError(f"no configuration with {target} antiparallel bonds")
+
+
+@pytest.mark.parametrize("name,over,std,counts", [
+    ("8x8_k4_m256", {"precision": "fp32"}, None, (72, 74, 78, 144)),
+    ("10x10_m400", {}, None, (216, 218, 222)),
+    ("6x6_fp32_eloc", {"n_hidden": 144, "irrep": "B1", "kx": 3, "ky": 3}, 0.1, (64, 66, 70)),
+])
+def test_wide_models_bond_pass_boundaries(name, over, std, counts):
+    """The wide kernel takes 4 x 18 bonds per pass at N >= 64 (4 x 16 at
+    N = 36) and skips the empty slot pairs of a partly filled last pass with a
+    bound taken from lane group 0 (bond i of a pass goes to lane group i mod 4).
+    Configurations whose antiparallel-bond count fills the passes exactly, or
+    carries 2, 4 or 6 bonds into a further pass (one more in some lane groups
+    than in others), checked row by row against the oracle's direct E_loc.  The
+    count is always even: every site has an even number of coupled bonds, and
+    the antiparallel ones are the bonds between the down spins and the rest."""
+    w = dataclasses.replace(WORKLOADS[name], **over)
+    p = draw_params(w) if std is None else stress_params(w, std, 31)
+    om = oracle.Model.from_workload(w)
+    sub = np.stack([_with_anti_count(om, n, 40 + k) for k, n in enumerate(counts)])
+    assert [_anti_count(om, s) for s in sub] == list(counts)
+    sp = np.concatenate([sub, random_sz0_spins(w.N, 5, 13)])
+    m = make(w, p)
+    glp, gel = m.eloc(cuda(sp))
+    rows = np.flatnonzero(nonzero_rows(om, p, sub))
+    assert len(rows) >= len(counts) - 1
+    tol = TOL[w.precision]
+    assert max_logpsi_err(glp.cpu().numpy()[rows], oracle.logpsi(om, p, sub[rows])) < tol
+    assert max_rel_err(gel.cpu().numpy()[rows], oracle.eloc_direct(om, p, sub[rows])) < tol
 
 
 # ------------------------------------------------------------ Sz = 0 sector
