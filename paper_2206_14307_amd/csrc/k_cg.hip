@@ -28,6 +28,7 @@ constexpr int kCgRows = 16;      // rows per block of the row GEMV
 constexpr int kRowParts = 8;     // most column parts of the complex64 row GEMV
 constexpr int kCgThreads = 256;
 constexpr int kVecThreads = 1024;
+constexpr int kCgBatch = 4;      // CG iterations queued per read of the residual
 
 struct cd {
   double x, y;
@@ -45,6 +46,11 @@ __device__ __forceinline__ float4 stream_load4(const float* p) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// The kernels of a CG iteration return at once once the solve has stopped
+// (stop = the flag cg_step_kernel sets; null outside the iteration), so the
+// host can queue several iterations per read of the residual.
+__device__ __forceinline__ bool stopped(const double* stop) { return stop != nullptr && *stop != 0.0; }
+
 template <typename RO>
 __device__ __forceinline__ cd load_c(const RO* p, size_t i) {
   return {(double)p[2 * i], (double)p[2 * i + 1]};
@@ -57,7 +63,9 @@ __global__ __launch_bounds__(kCgThreads) void rows_kernel(const RO* __restrict__
                                                           int64_t P, const double* __restrict__ v,
                                                           const double* __restrict__ mv,
                                                           double inv_sqrt_s,
-                                                          double* __restrict__ u) {
+                                                          double* __restrict__ u,
+                                                          const double* __restrict__ stop) {
+  if (stopped(stop)) return;
   __shared__ double red[kCgRows][2][kCgThreads / 64];
   const int64_t s0 = (int64_t)blockIdx.x * kCgRows;
   double ar[kCgRows], ai[kCgRows];
@@ -102,7 +110,9 @@ template <typename RO>
 __global__ __launch_bounds__(kCgThreads) void cols_kernel(const RO* __restrict__ O, int64_t S,
                                                           int64_t P, int64_t slab,
                                                           const double* __restrict__ u,
-                                                          double* __restrict__ part) {
+                                                          double* __restrict__ part,
+                                                          const double* __restrict__ stop) {
+  if (stopped(stop)) return;
   const int64_t k = (int64_t)blockIdx.x * kCgThreads + threadIdx.x;
   const int64_t sb = (int64_t)blockIdx.y * slab, se = std::min<int64_t>(S, sb + slab);
   if (k >= P) return;
@@ -125,7 +135,9 @@ __global__ __launch_bounds__(kCgThreads) void cols_kernel(const RO* __restrict__
 // small part of the pass.
 __global__ __launch_bounds__(kCgThreads) void rows2_kernel(const float* __restrict__ O, int64_t S,
                                                            int64_t P, const double* __restrict__ v,
-                                                           double* __restrict__ upart) {
+                                                           double* __restrict__ upart,
+                                                           const double* __restrict__ stop) {
+  if (stopped(stop)) return;
   __shared__ double red[kCgRows][2][kCgThreads / 64];
   const int64_t s0 = (int64_t)blockIdx.x * kCgRows;
   const int64_t P2 = P / 2;
@@ -176,7 +188,9 @@ __global__ __launch_bounds__(kCgThreads) void rows2_finish_kernel(const double* 
                                                                   int parts, int64_t S,
                                                                   const double* __restrict__ mv,
                                                                   double inv_sqrt_s,
-                                                                  double* __restrict__ u) {
+                                                                  double* __restrict__ u,
+                                                                  const double* __restrict__ stop) {
+  if (stopped(stop)) return;
   const int64_t s = (int64_t)blockIdx.x * kCgThreads + threadIdx.x;
   if (s >= S) return;
   double sr = 0.0, si = 0.0;
@@ -193,7 +207,9 @@ __global__ __launch_bounds__(kCgThreads) void rows2_finish_kernel(const double* 
 __global__ __launch_bounds__(kCgThreads) void cols2_kernel(const float* __restrict__ O, int64_t S,
                                                            int64_t P, int64_t slab,
                                                            const double* __restrict__ u,
-                                                           double* __restrict__ part) {
+                                                           double* __restrict__ part,
+                                                           const double* __restrict__ stop) {
+  if (stopped(stop)) return;
   const int64_t k2 = (int64_t)blockIdx.x * kCgThreads + threadIdx.x;
   const int64_t sb = (int64_t)blockIdx.y * slab, se = std::min<int64_t>(S, sb + slab);
   if (k2 >= P / 2) return;
@@ -252,7 +268,8 @@ __device__ double vsum(double v, double* red) {
 __global__ __launch_bounds__(kCgThreads) void slab_sum_kernel(
     const double* __restrict__ part, int nslab, int64_t P, int mode, double S_or_invsqrt,
     const double* __restrict__ m, const double* __restrict__ usum, double scale, double lambda,
-    const double* __restrict__ p, double* __restrict__ out) {
+    const double* __restrict__ p, double* __restrict__ out, const double* __restrict__ stop) {
+  if (stopped(stop)) return;
   const int64_t k = (int64_t)blockIdx.x * kCgThreads + threadIdx.x;
   if (k >= P) return;
   double qr = 0.0, qi = 0.0;
@@ -309,7 +326,9 @@ __global__ __launch_bounds__(kVecThreads) void eps_kernel(const double* __restri
 // usum_kernel.
 __global__ __launch_bounds__(kVecThreads) void mdot_kernel(const double* __restrict__ m,
                                                            const double* __restrict__ v, int64_t P,
-                                                           double* __restrict__ scal) {
+                                                           double* __restrict__ scal,
+                                                           const double* __restrict__ stop) {
+  if (stopped(stop)) return;
   __shared__ double red[kVecThreads];
   double sr = 0.0, si = 0.0;
   for (int64_t k = threadIdx.x; k < P; k += kVecThreads) {
@@ -328,7 +347,9 @@ __global__ __launch_bounds__(kVecThreads) void mdot_kernel(const double* __restr
 
 // scal[2..3] = sum_s u_s.
 __global__ __launch_bounds__(kVecThreads) void usum_kernel(const double* __restrict__ u, int64_t S,
-                                                           double* __restrict__ scal) {
+                                                           double* __restrict__ scal,
+                                                           const double* __restrict__ stop) {
+  if (stopped(stop)) return;
   __shared__ double red[kVecThreads];
   double sr = 0.0, si = 0.0;
   for (int64_t i = threadIdx.x; i < S; i += kVecThreads) {
@@ -363,17 +384,23 @@ __global__ __launch_bounds__(kVecThreads) void cg_init_kernel(const double* __re
     cg[0] = s;
     cg[1] = s;
     cg[2] = 0.0;
+    cg[3] = 0.0;
+    cg[4] = 0.0;
   }
 }
 
 // One CG update given q = A p: alpha = rr / (p^H q), x += alpha p,
 // r -= alpha q, beta = rr' / rr, p = r + beta p.  cg[0] = rr', cg[2] = 1
-// if p^H q <= 0 (A not positive definite along p).
+// if p^H q <= 0 (A not positive definite along p); cg[4] counts the
+// iterations and cg[3] = 1 stops the solve (not positive definite, or
+// rr' <= thr2 = tol^2 b^H b).
 __global__ __launch_bounds__(kVecThreads) void cg_step_kernel(double* __restrict__ x,
                                                               double* __restrict__ r,
                                                               double* __restrict__ p,
                                                               const double* __restrict__ q,
-                                                              int64_t P, double* __restrict__ cg) {
+                                                              int64_t P, double* __restrict__ cg,
+                                                              double thr2) {
+  if (cg[3] != 0.0) return;
   __shared__ double red[kVecThreads];
   double s = 0.0;
   for (int64_t k = threadIdx.x; k < P; k += kVecThreads)
@@ -381,7 +408,11 @@ __global__ __launch_bounds__(kVecThreads) void cg_step_kernel(double* __restrict
   const double pq = vsum(s, red);
   const double rr = cg[0];
   if (!(pq > 0.0)) {
-    if (threadIdx.x == 0) cg[2] = 1.0;
+    if (threadIdx.x == 0) {
+      cg[2] = 1.0;
+      cg[3] = 1.0;
+      cg[4] += 1.0;
+    }
     return;
   }
   const double alpha = rr / pq;
@@ -401,7 +432,11 @@ __global__ __launch_bounds__(kVecThreads) void cg_step_kernel(double* __restrict
     p[2 * k] = fma(beta, p[2 * k], r[2 * k]);
     p[2 * k + 1] = fma(beta, p[2 * k + 1], r[2 * k + 1]);
   }
-  if (threadIdx.x == 0) cg[0] = rr2;
+  if (threadIdx.x == 0) {
+    cg[0] = rr2;
+    cg[4] += 1.0;
+    if (!(rr2 > thr2)) cg[3] = 1.0;
+  }
 }
 
 struct CgLayout {
@@ -438,13 +473,13 @@ CgLayout cg_layout(const nqs_ctx* c, int64_t S) {
 
 template <typename RO>
 hipError_t cols_to(const RO* O, int64_t S, int64_t P, const CgLayout& L, const double* u,
-                   double* part, hipStream_t st) {
+                   double* part, const double* stop, hipStream_t st) {
   if constexpr (sizeof(RO) == 4) {
     const dim3 grid((unsigned)((P / 2 + kCgThreads - 1) / kCgThreads), (unsigned)L.nslab);
-    cols2_kernel<<<grid, kCgThreads, 0, st>>>(O, S, P, L.slab, u, part);
+    cols2_kernel<<<grid, kCgThreads, 0, st>>>(O, S, P, L.slab, u, part, stop);
   } else {
     const dim3 grid((unsigned)((P + kCgThreads - 1) / kCgThreads), (unsigned)L.nslab);
-    cols_kernel<RO><<<grid, kCgThreads, 0, st>>>(O, S, P, L.slab, u, part);
+    cols_kernel<RO><<<grid, kCgThreads, 0, st>>>(O, S, P, L.slab, u, part, stop);
   }
   return hipGetLastError();
 }
@@ -470,50 +505,58 @@ hipError_t cg_run(nqs_ctx* c, const RO* O, const double* eloc, int64_t S, double
   const double is = 1.0 / std::sqrt((double)S);
   hipError_t e;
   // mean m = <O>
-  if ((e = cols_to(O, S, P, L, nullptr, part, st)) != hipSuccess) return e;
+  if ((e = cols_to(O, S, P, L, nullptr, part, nullptr, st)) != hipSuccess) return e;
   slab_sum_kernel<<<ptiles, kCgThreads, 0, st>>>(part, (int)L.nslab, P, 0, (double)S, nullptr,
-                                                 nullptr, 1.0, 0.0, nullptr, m);
+                                                 nullptr, 1.0, 0.0, nullptr, m, nullptr);
   // eps and b = -dtau O_bar^H eps
   eps_kernel<<<1, kVecThreads, 0, st>>>(eloc, S, eps, scal);
-  if ((e = cols_to(O, S, P, L, eps, part, st)) != hipSuccess) return e;
+  if ((e = cols_to(O, S, P, L, eps, part, nullptr, st)) != hipSuccess) return e;
   slab_sum_kernel<<<ptiles, kCgThreads, 0, st>>>(part, (int)L.nslab, P, 1, is, m, scal + 2, -dtau,
-                                                 0.0, nullptr, b);
+                                                 0.0, nullptr, b, nullptr);
   cg_init_kernel<<<1, kVecThreads, 0, st>>>(b, P, x, r, p, cg);
-  double h[3];
-  if ((e = hipMemcpyAsync(h, cg, 24, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  double h[5];
+  if ((e = hipMemcpyAsync(h, cg, 40, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
   const double bb = h[1];
-  double rr = h[0];
-  int it = 0;
-  while (it < max_iter && bb > 0.0 && rr > tol * tol * bb) {
-    // q = A p
-    mdot_kernel<<<1, kVecThreads, 0, st>>>(m, p, P, scal);
-    if constexpr (sizeof(RO) == 4) {
-      // column parts of at least four sweeps of the block over column pairs
-      const int parts = (int)std::max<int64_t>(
-          1, std::min<int64_t>(kRowParts, P / 2 / (4 * kCgThreads)));
-      const dim3 rgrid((unsigned)((S + kCgRows - 1) / kCgRows), (unsigned)parts);
-      rows2_kernel<<<rgrid, kCgThreads, 0, st>>>(O, S, P, p, upart);
-      rows2_finish_kernel<<<(unsigned)((S + kCgThreads - 1) / kCgThreads), kCgThreads, 0, st>>>(
-          upart, parts, S, scal, is, u);
-    } else
-      rows_kernel<RO><<<(unsigned)((S + kCgRows - 1) / kCgRows), kCgThreads, 0, st>>>(O, S, P, p,
-                                                                                   scal, is, u);
-    usum_kernel<<<1, kVecThreads, 0, st>>>(u, S, scal);
-    if ((e = cols_to(O, S, P, L, u, part, st)) != hipSuccess) return e;
-    slab_sum_kernel<<<ptiles, kCgThreads, 0, st>>>(part, (int)L.nslab, P, 1, is, m, scal + 2, 1.0,
-                                                   lambda, p, q);
-    cg_step_kernel<<<1, kVecThreads, 0, st>>>(x, r, p, q, P, cg);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(h, cg, 24, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    ++it;
-    if (h[2] != 0.0) {
-      *not_pd = 1;
-      break;
+  const double thr2 = tol * tol * bb;
+  // iterations are queued kCgBatch at a time; those after the stop return at
+  // once, so the iterates and the count equal a check after every iteration
+  int issued = 0;
+  if (bb > 0.0 && h[0] > thr2) {
+    const double* stop = cg + 3;
+    while (issued < max_iter) {
+      const int nb = std::min(kCgBatch, max_iter - issued);
+      for (int j = 0; j < nb; ++j) {
+        // q = A p
+        mdot_kernel<<<1, kVecThreads, 0, st>>>(m, p, P, scal, stop);
+        if constexpr (sizeof(RO) == 4) {
+          // column parts of at least four sweeps of the block over column pairs
+          const int parts = (int)std::max<int64_t>(
+              1, std::min<int64_t>(kRowParts, P / 2 / (4 * kCgThreads)));
+          const dim3 rgrid((unsigned)((S + kCgRows - 1) / kCgRows), (unsigned)parts);
+          rows2_kernel<<<rgrid, kCgThreads, 0, st>>>(O, S, P, p, upart, stop);
+          rows2_finish_kernel<<<(unsigned)((S + kCgThreads - 1) / kCgThreads), kCgThreads, 0,
+                                st>>>(upart, parts, S, scal, is, u, stop);
+        } else {
+          rows_kernel<RO><<<(unsigned)((S + kCgRows - 1) / kCgRows), kCgThreads, 0, st>>>(
+              O, S, P, p, scal, is, u, stop);
+        }
+        usum_kernel<<<1, kVecThreads, 0, st>>>(u, S, scal, stop);
+        if ((e = cols_to(O, S, P, L, u, part, stop, st)) != hipSuccess) return e;
+        slab_sum_kernel<<<ptiles, kCgThreads, 0, st>>>(part, (int)L.nslab, P, 1, is, m, scal + 2,
+                                                       1.0, lambda, p, q, stop);
+        cg_step_kernel<<<1, kVecThreads, 0, st>>>(x, r, p, q, P, cg, thr2);
+      }
+      issued += nb;
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = hipMemcpyAsync(h, cg, 40, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+      if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+      if (h[3] != 0.0) break;
     }
-    rr = h[0];
   }
+  const int it = (int)h[4];
+  if (h[2] != 0.0) *not_pd = 1;
+  const double rr = h[0];
   *iters = it;
   *resid = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
   return hipSuccess;

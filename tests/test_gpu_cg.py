@@ -93,3 +93,23 @@ def test_cg_edges(c1_inputs):
         m.sr_solve_cg(Ot, et, lam=-1.0)
     with pytest.raises(NQSError):
         m.sr_solve_cg(Ot, et, tol=-1.0)
+
+
+def test_cg_stops_exactly_within_a_queued_batch(c1_inputs):
+    """The library queues several CG iterations per read of the residual and
+    the ones after the stop do nothing: a solve that converges at iteration n
+    returns n, and its iterate equals, bit for bit, the one capped at
+    max_iter = n; caps that are not multiples of the batch return exactly that
+    many iterations."""
+    w, O, el = c1_inputs
+    m = make(w)
+    Ot, et = torch.from_numpy(O[:200]).cuda(), torch.from_numpy(el[:200]).cuda()
+    kw = dict(lam=1e-3, dtau=0.02, tol=1e-10)
+    x, n, res = m.sr_solve_cg(Ot, et, max_iter=5000, **kw)
+    assert 1 <= n < 5000 and res <= 1e-10
+    xc, nc, resc = m.sr_solve_cg(Ot, et, max_iter=n, **kw)
+    assert nc == n and resc == res and torch.equal(xc, x)
+    for k in (1, 2, 3, 5, 6, 7, 9):
+        if k < n:
+            xk, nk, rk = m.sr_solve_cg(Ot, et, max_iter=k, **kw)
+            assert nk == k and rk > 1e-10
