@@ -50,7 +50,8 @@ typedef enum {
     NQS_ERR_OOM = 3,          /* the context could not allocate its tables */
     NQS_ERR_NONFINITE = 4,    /* non-finite parameters or non-finite moments */
     NQS_WARN_DEGENERATE = 5,  /* Lanczos: zero variance (eigenstate); e_p1 = h1, alpha = 0 */
-    NQS_ERR_NOT_PD = 6        /* SR: the Gram matrix is not positive definite */
+    NQS_ERR_NOT_PD = 6,       /* SR: the Gram matrix is not positive definite */
+    NQS_WARN_NOT_CONVERGED = 7 /* CG stopped at max_iter above tol; the result is the last iterate */
 } nqs_status;
 
 typedef enum {
@@ -210,8 +211,12 @@ nqs_status nqs_sr_solve(nqs_ctx* ctx, const void* O, const double* eloc, int64_t
  * when ||r|| <= tol ||b|| or after max_iter iterations.  O, eloc and
  * dtheta_out as in nqs_sr_solve; iters_out and resid_out (host, optional)
  * receive the iteration count and ||r|| / ||b||.  Workspace:
- * nqs_workspace_bytes(NQS_OP_CG, S).  Synchronises the stream (once per
- * iteration, to test the residual); NQS_ERR_NOT_PD if p^H A p <= 0. */
+ * nqs_workspace_bytes(NQS_OP_CG, S).  Synchronises the stream: iterations
+ * are queued four at a time and the residual is read once per four (a
+ * device-side flag ends the queued ones after the stop, so the iterates and
+ * the count equal a test after every iteration).  NQS_ERR_NOT_PD if
+ * p^H A p <= 0; NQS_WARN_NOT_CONVERGED (dtheta_out holds the last iterate)
+ * if ||r|| > tol ||b|| after max_iter iterations. */
 nqs_status nqs_sr_solve_cg(nqs_ctx* ctx, const void* O, const double* eloc, int64_t S,
                            double lambda, double dtau, double tol, int max_iter,
                            double* dtheta_out, int* iters_out, double* resid_out, void* ws,
@@ -259,7 +264,9 @@ nqs_status nqs_get_params(nqs_ctx* ctx, double* params_out_dev, hipStream_t stre
  * describes the parameters before the update.  Workspace:
  * nqs_workspace_bytes(NQS_OP_VMC, S).  Synchronises the stream.  Errors are
  * those of the three calls; NQS_ERR_NONFINITE (parameters unchanged) if
- * theta + dtheta is not finite. */
+ * theta + dtheta is not finite.  NQS_WARN_NOT_CONVERGED when CG stopped
+ * above its tolerance: the update from its last iterate is still applied
+ * and out->solver_resid says how far it got. */
 nqs_status nqs_vmc_step(nqs_ctx* ctx, const int8_t* spins, int64_t S, double lambda, double dtau,
                         int real_params, int solver, nqs_vmc_stats* out, void* ws,
                         size_t ws_bytes, hipStream_t stream);

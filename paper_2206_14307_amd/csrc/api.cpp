@@ -235,6 +235,7 @@ const char* nqs_status_str(nqs_status s) {
     case NQS_ERR_NONFINITE: return "non-finite value";
     case NQS_WARN_DEGENERATE: return "degenerate Lanczos step (zero variance)";
     case NQS_ERR_NOT_PD: return "matrix not positive definite";
+    case NQS_WARN_NOT_CONVERGED: return "iterative solver stopped above its tolerance";
   }
   return "unknown status";
 }
@@ -463,7 +464,8 @@ nqs_status nqs_vmc_step(nqs_ctx* c, const int8_t* spins, int64_t S, double lambd
   s = solver == 0 ? nqs_sr_solve(c, O, eloc, S, lambda, dtau, dth, sub, sub_bytes, st)
                   : nqs_sr_solve_cg(c, O, eloc, S, lambda, dtau, 1e-8, 2000, dth, &iters, &resid,
                                     sub, sub_bytes, st);
-  if (s != NQS_OK) return s;
+  const bool unconverged = s == NQS_WARN_NOT_CONVERGED;
+  if (s != NQS_OK && !unconverged) return s;
   if ((e = launch_params_step(c->par.params, dth, c->P, real_params ? 0 : 1, next, stats, st)) !=
       hipSuccess)
     return hip_fail(c, e, "parameter step");
@@ -484,6 +486,10 @@ nqs_status nqs_vmc_step(nqs_ctx* c, const int8_t* spins, int64_t S, double lambd
       hipSuccess)
     return hip_fail(c, e, "memcpy params");
   if ((e = prep_tables(c, st)) != hipSuccess) return hip_fail(c, e, "prep");
+  if (unconverged)
+    return fail(c, NQS_WARN_NOT_CONVERGED,
+                "vmc_step: CG stopped above its tolerance (relative residual " +
+                    std::to_string(resid) + "); the update was applied");
   return NQS_OK;
 }
 

@@ -12,8 +12,11 @@
 //         rows; the part sums are added in a fixed order;
 //   cols: q_k = sum_s conj(O_sk) u_s, a block takes 256 columns and one slab
 //         of rows; slab partials are added in a fixed order.
-// The CG scalars stay on the device (single-block FP64 kernels); the host
-// reads the residual once per iteration to stop.  All sums in FP64.
+// The CG scalars stay on the device (single-block FP64 kernels).  Iterations
+// are queued kCgBatch at a time: a device-side flag set when the residual
+// test passes makes the rest of the batch return at once, and the host reads
+// the residual once per batch (same iterates and count as a test after every
+// iteration).  All sums in FP64.
 #include <algorithm>
 #include <cmath>
 
@@ -599,6 +602,10 @@ extern "C" nqs_status nqs_sr_solve_cg(nqs_ctx* c, const void* O, const double* e
   if (resid_out) *resid_out = resid;
   if (e != hipSuccess) return fail(NQS_ERR_DEVICE, std::string("sr_solve_cg: ") + hipGetErrorString(e));
   if (not_pd) return fail(NQS_ERR_NOT_PD, "sr_solve_cg: p^H A p <= 0");
+  if (!(resid <= tol))
+    return fail(NQS_WARN_NOT_CONVERGED, "sr_solve_cg: relative residual " + std::to_string(resid) +
+                                            " above tol after " + std::to_string(iters) +
+                                            " iterations");
   return NQS_OK;
 }
 

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnqs.so")
 
 NQS_OK, NQS_ERR_ARG, NQS_ERR_DEVICE, NQS_ERR_OOM, NQS_ERR_NONFINITE, NQS_WARN_DEGENERATE, \
-    NQS_ERR_NOT_PD = range(7)
+    NQS_ERR_NOT_PD, NQS_WARN_NOT_CONVERGED = range(8)
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 IRREP = {"A1": 0, "A2": 1, "B1": 2, "B2": 3}
 OP = {"logpsi": 0, "eloc": 1, "moments": 2, "grad": 3, "sr": 4, "sample": 5, "sq": 6, "vmc": 7, "cg": 8,
@@ -139,6 +139,7 @@ class NQS:
             raise NQSError(st, f"nqs_create failed: {self.lib.nqs_status_str(st).decode()}")
         self.P = int(self.lib.nqs_num_params(self._ctx))
         self._ws = None
+        self.last_status = NQS_OK
 
     @classmethod
     def from_workload(cls, w, device="cuda"):
@@ -158,7 +159,10 @@ class NQS:
 
     # -------------------------------------------------------------- helpers
     def _check(self, st, what):
-        if st not in (NQS_OK, NQS_WARN_DEGENERATE):
+        """Raise on an error status; warnings (degenerate Lanczos step, CG
+        stopped above its tolerance) are kept in ``last_status``."""
+        self.last_status = st
+        if st not in (NQS_OK, NQS_WARN_DEGENERATE, NQS_WARN_NOT_CONVERGED):
             msg = self.lib.nqs_last_error(self._ctx).decode()
             raise NQSError(st, f"{what}: {self.lib.nqs_status_str(st).decode()}: {msg}")
         return st
@@ -374,14 +378,33 @@ class NQS:
 class LogPsi(torch.autograd.Function):
     """log psi(sigma; theta) with the hand-written backward O_k (nqs_grad).
 
+    ``LogPsi.apply(params, spins, model)`` evaluates log psi at ``params``
+    (complex [P], or real [P] for a real RBM) and leaves the context's own
+    parameters as they were.  The forward forms O_k (nqs_grad) only when a
+    gradient with respect to params is wanted, else it calls nqs_logpsi.
+
     PyTorch's complex convention: for the holomorphic map theta -> log psi,
-    the vector-Jacobian product is grad_theta_k = sum_s grad_out[s] conj(O[s, k])."""
+    the vector-Jacobian product is grad_theta_k = sum_s grad_out[s] conj(O[s, k]);
+    for real parameters it is the real part of that sum."""
 
     @staticmethod
     def forward(ctx, params, spins, model):
-        model.set_params(params.detach())
-        O, lp = model.grad(spins, want_logpsi=True)
-        ctx.save_for_backward(O)
+        prev = model.get_params()
+        p = params.detach().reshape(-1).to(device=prev.device, dtype=torch.complex128)
+        changed = not torch.equal(prev, p)
+        if changed:
+            model.set_params(p)
+        try:
+            if ctx.needs_input_grad[0]:
+                O, lp = model.grad(spins, want_logpsi=True)
+                ctx.save_for_backward(O)
+            else:
+                lp = model.logpsi(spins)
+        finally:
+            if changed:
+                model.set_params(prev)
+        ctx.real_params = not params.is_complex()
+        ctx.shape, ctx.dtype = params.shape, params.dtype
         return lp
 
     @staticmethod
@@ -389,4 +412,6 @@ class LogPsi(torch.autograd.Function):
         (O,) = ctx.saved_tensors
         g = grad_out.to(torch.complex128)
         gp = (g[:, None] * O.to(torch.complex128).conj()).sum(dim=0)
-        return gp, None, None
+        if ctx.real_params:
+            gp = gp.real
+        return gp.reshape(ctx.shape).to(ctx.dtype), None, None

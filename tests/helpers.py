@@ -64,3 +64,69 @@ def reciprocal_form_in_range(model, params, lg=96.0):
             if not ((suf >= -lg) & (suf <= lg)).all():
                 return False
     return True
+
+
+# ---------------------------------------------------------------- error model
+#
+# The tolerances bound the error relative to the size of what is summed, not
+# to the size of the sum.  E_loc = H_ss + sum_b (J_b/2) psi(s^b)/psi(s), each
+# psi(s^b) itself a sum over the images; when the terms are large and cancel
+# (stress parameters, non-A1 irreps), rounding of the terms, not of the result,
+# sets the attainable error.  The scale is therefore
+#   kappa_E(s) = |H_ss| + sum_b |J_b/2| sum_{k,g} |psi_s^(k)(g s^b)| / |psi(s)|,
+# and for a log-derivative row O_s (sums over images of w t x) the
+# componentwise bound uses sum_{k,g} |w_kg| |t_kgh| |x_gj|.  Both equal |E_loc|
+# and ||O_s|| when nothing cancels.
+
+def eloc_error_scale(model, params, spins):
+    """kappa_E per configuration (see above), from the oracle's per-image
+    amplitudes of every exchange neighbour (no division by psi(s^b), which
+    may vanish)."""
+    import oracle
+    spins = np.atleast_2d(np.asarray(spins))
+    lp = oracle.logpsi(model, params, spins)
+    diag = oracle.diag_energy(model, spins)
+    bi, bj = model.lat.bonds[:, 0], model.lat.bonds[:, 1]
+    out = np.empty(len(spins))
+    for r, s in enumerate(spins):
+        anti = np.nonzero(s[bi] != s[bj])[0]
+        conn = np.repeat(s[None, :], len(anti), axis=0)
+        rows = np.arange(len(anti))
+        conn[rows, bi[anti]], conn[rows, bj[anti]] = s[bj[anti]], s[bi[anti]]
+        Xg = oracle.images(model, conn)
+        tot = np.zeros(len(anti))
+        for (W, a, b) in model.split(params):
+            ls = oracle.logpsi_s(Xg, W, a, b)
+            tot += np.exp(ls.real - lp[r].real).sum(axis=1)
+        out[r] = abs(diag[r]) + (0.5 * np.abs(model.bond_J[anti]) * tot).sum()
+    return out
+
+
+def max_scaled_eloc_err(got, ref, scale):
+    """max_s |got - ref| / max(1, kappa_E(s))."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    return float((np.abs(got - ref) / np.maximum(1.0, np.asarray(scale))).max())
+
+
+def grad_error_scale(model, params, spins):
+    """||sum_{k,g} |w_kg| |t_kgh| |x_gj| ||_2 per configuration, over the
+    same [W | a | b] layout as the oracle's log-derivatives."""
+    import oracle
+    w, t, Xg = oracle.image_weights(model, params, spins)
+    aw, at, ax = np.abs(w), np.abs(t), np.abs(Xg)
+    S = Xg.shape[0]
+    parts = []
+    for k in range(model.n_rbm):
+        wt = aw[:, k, :, None] * at[:, k]
+        parts.append(np.einsum("sgh,sgj->shj", wt, ax).reshape(S, -1))
+        if model.use_bias:
+            parts.append(np.einsum("sg,sgj->sj", aw[:, k], ax))
+            parts.append(wt.sum(axis=1))
+    return np.linalg.norm(np.concatenate(parts, axis=1), axis=1)
+
+
+def max_scaled_row_err(A, B, scale):
+    """max_s ||A_s - B_s|| / max(||B_s||, scale_s)."""
+    A, B = np.asarray(A), np.asarray(B)
+    den = np.maximum(np.linalg.norm(B, axis=1), np.asarray(scale))
+    return float((np.linalg.norm(A - B, axis=1) / den).max())

@@ -59,5 +59,6 @@ def test_status_strings_without_a_device(lib_path):
     lib = load_library()
     assert lib.nqs_status_str(0) == b"ok"
     assert lib.nqs_status_str(6).startswith(b"matrix")
+    assert lib.nqs_status_str(7).startswith(b"iterative solver")
     assert lib.nqs_num_params(None) == -1
     assert lib.nqs_workspace_bytes(None, 0, 10) == 0

@@ -89,6 +89,10 @@ def test_cg_edges(c1_inputs):
     Ot, et = torch.from_numpy(O[:10]).cuda(), torch.from_numpy(el[:10]).cuda()
     x, it, res = m.sr_solve_cg(Ot, et, lam=1e-3, dtau=0.02, tol=1e-12, max_iter=0)
     assert it == 0 and res == pytest.approx(1.0) and torch.count_nonzero(x) == 0
+    from paper_2206_14307_amd.nqs import NQS_OK, NQS_WARN_NOT_CONVERGED
+    assert m.last_status == NQS_WARN_NOT_CONVERGED          # stopped above tol: a warning
+    m.sr_solve_cg(Ot, et, lam=1e-3, dtau=0.02, tol=1e-8, max_iter=5000)
+    assert m.last_status == NQS_OK
     with pytest.raises(NQSError):
         m.sr_solve_cg(Ot, et, lam=-1.0)
     with pytest.raises(NQSError):

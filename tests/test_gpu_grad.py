@@ -88,3 +88,56 @@ def test_grad_full_size_sampled_rows():
     assert max_row_rel_err(Os, oracle.logderiv(om, p, sp[rows])) < TOL["fp32"]
     assert max_logpsi_err(lp.cpu().numpy()[rows], oracle.logpsi(om, p, sp[rows])) < TOL["fp32"]
     del O
+
+
+LOGPSI_CASES = {
+    # name: (workload, overrides, parameter std or None for the drawn ones)
+    "6x6_m16_fp32_complex": ("6x6_fp32_eloc", {"n_hidden": 16}, 0.1),
+    "4x4_fp64_real": ("4x4_fp64_exact", {}, None),
+}
+
+
+@pytest.mark.parametrize("case", list(LOGPSI_CASES))
+def test_logpsi_autograd_function(case):
+    """LogPsi (torch.autograd.Function over nqs_logpsi / nqs_grad): the gradient
+    of L = Re sum_s c_s log psi_s, for random complex c, equals
+    conj(sum_s c_s O_sk) (its real part for a real RBM) with the oracle's
+    log-derivatives, and central finite differences of the oracle's log psi
+    along Re and Im of a few parameters; the forward equals the oracle's
+    log psi and leaves the context's parameters unchanged."""
+    from paper_2206_14307_amd import LogPsi
+    name, over, std = LOGPSI_CASES[case]
+    w = dataclasses.replace(WORKLOADS[name], **over)
+    p = draw_params(w) if std is None else stress_params(w, std, 13)
+    om = oracle.Model.from_workload(w)
+    sp = random_sz0_spins(w.N, 9, 17)
+    sp = sp[nonzero_rows(om, p, sp)]
+    rng = np.random.default_rng(3)
+    c = rng.normal(size=len(sp)) + 1j * rng.normal(size=len(sp))
+    m = make(w, np.zeros_like(p))                       # the context holds other parameters
+    before = m.get_params().cpu().numpy()
+    pt = torch.from_numpy(p.reshape(-1) if w.is_complex else p.reshape(-1).real.copy())
+    pt = pt.cuda().requires_grad_(True)
+    lp = LogPsi.apply(pt, cuda(sp), m)
+    assert np.array_equal(m.get_params().cpu().numpy(), before)
+    tol = TOL[w.precision]
+    assert max_logpsi_err(lp.detach().cpu().numpy(), oracle.logpsi(om, p, sp)) < tol
+    L = (torch.from_numpy(c).cuda() * lp).real.sum()
+    (g,) = torch.autograd.grad(L, pt)
+    g = g.cpu().numpy()
+    assert g.dtype == (np.complex128 if w.is_complex else np.float64)
+    cO = (c[:, None] * oracle.logderiv(om, p, sp)).sum(axis=0)
+    ref = np.conj(cO) if w.is_complex else cO.real
+    assert np.linalg.norm(g - ref) < tol * np.linalg.norm(ref)
+    # finite differences of the oracle along the real (and imaginary) direction
+    idx = np.r_[0, 7, len(ref) // 2, len(ref) - 1]
+    fd = (c[:, None] * oracle.logderiv_fd(om, p, sp, indices=idx)).sum(axis=0)
+    fd_tol = max(tol, 1e-8)
+    assert np.abs(g[idx].real - fd.real).max() < fd_tol * np.abs(ref).max()
+    if w.is_complex:
+        # d L / d Im p_k = Re sum_s c_s (i O_sk) = -Im sum_s c_s O_sk = Im g_k
+        assert np.abs(g[idx].imag + fd.imag).max() < fd_tol * np.abs(ref).max()
+    # no gradient wanted: log psi alone (no O formed), same values
+    with torch.no_grad():
+        lp2 = LogPsi.apply(pt.detach(), cuda(sp), m)
+    assert max_logpsi_err(lp2.cpu().numpy(), lp.detach().cpu().numpy()) < tol

@@ -12,7 +12,8 @@ import pytest
 import torch
 
 import oracle
-from helpers import (TOL, max_logpsi_err, max_rel_err, max_row_rel_err, nonzero_rows,
+from helpers import (TOL, eloc_error_scale, grad_error_scale, max_logpsi_err, max_rel_err,
+                     max_row_rel_err, max_scaled_eloc_err, max_scaled_row_err, nonzero_rows,
                      reciprocal_form_in_range, stress_params)
 from workloads import WORKLOADS, draw_params, random_sz0_spins
 
@@ -106,9 +107,13 @@ def test_stress_fp64(irrep, k, sector16):
     m = make(w, p)
     glp, gel = m.eloc(cuda(sp))
     assert max_logpsi_err(glp.cpu().numpy(), oracle.logpsi(om, p, sp)) < TOL["fp64"]
-    assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp)) < 1e-9
+    # std-0.3 parameters: the exchange terms and image sums cancel, so the
+    # errors are gated against the size of the terms (helpers' error model)
+    kE = eloc_error_scale(om, p, sp)
+    assert max_scaled_eloc_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp), kE) < TOL["fp64"]
     O = m.grad(cuda(sp[:12])).cpu().numpy()
-    assert max_row_rel_err(O, oracle.logderiv(om, p, sp[:12])) < 1e-9
+    kO = grad_error_scale(om, p, sp[:12])
+    assert max_scaled_row_err(O, oracle.logderiv(om, p, sp[:12]), kO) < TOL["fp64"]
 
 
 # ------------------------------------------------------------------ 6x6 FP32
@@ -150,7 +155,11 @@ def test_stress_fp32_b1_pi():
     m = make(w, p)
     glp, gel = m.eloc(cuda(sp))
     assert max_logpsi_err(glp.cpu().numpy(), oracle.logpsi(om, p, sp)) < TOL["fp32"]
-    assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp)) < 1e-4
+    kE = eloc_error_scale(om, p, sp)
+    assert max_scaled_eloc_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp), kE) < TOL["fp32"]
+    O = m.grad(cuda(sp)).cpu().numpy()
+    kO = grad_error_scale(om, p, sp)
+    assert max_scaled_row_err(O, oracle.logderiv(om, p, sp), kO) < TOL["fp32"]
 
 
 @pytest.mark.parametrize("direct", [False, True])

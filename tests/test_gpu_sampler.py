@@ -44,13 +44,32 @@ def compare_trajectories(gpu, ref, log, n_per_chain, tie_tol):
     return diverged
 
 
-@pytest.mark.parametrize("name,std,tie", [("4x4_fp64_exact", 0.3, 1e-10),
-                                          ("6x6_fp32_eloc", 0.2, 2e-5)])
-def test_trajectory_replay(name, std, tie):
-    w = dataclasses.replace(WORKLOADS[name], is_complex=True)
+# (workload, overrides, parameter std, near-tie tolerance, chains, samples per
+# chain, N_skip, burn-in).  The FP64 4x4 case runs the cache-streaming kernel
+# in double precision; the 6x6 M = 72 case the register kernel; every other
+# case (K > 1, or M outside the register kernel's sizes, as for the 8x8 and
+# 10x10 workloads) the FP32 cache-streaming kernel.  The 4x4 FP32 and 6x6
+# K = 2 runs cross the cache refresh after 256 proposals; the 10x10 runs use
+# the high word of the spin bits (N > 64).
+REPLAY = {
+    "4x4_fp64": ("4x4_fp64_exact", {"is_complex": True}, 0.3, 1e-10, 6, 12, 3, 10),
+    "6x6_m72_reg": ("6x6_fp32_eloc", {}, 0.2, 2e-5, 6, 12, 3, 10),
+    "4x4_fp32_k2_m8": ("4x4_fp64_exact", {"is_complex": True, "precision": "fp32", "n_rbm": 2,
+                                          "n_hidden": 8}, 0.3, 2e-5, 6, 12, 3, 250),
+    "6x6_k2_m16": ("6x6_fp32_eloc", {"n_rbm": 2, "n_hidden": 16}, 0.2, 2e-5, 3, 12, 3, 250),
+    "8x8_k4_m256_fp32": ("8x8_k4_m256", {"precision": "fp32"}, 0.08, 2e-5, 2, 4, 3, 8),
+    "10x10_m400_fp32": ("10x10_m400", {"precision": "fp32"}, 0.08, 2e-5, 2, 4, 3, 8),
+    "10x10_m400_bf16x2": ("10x10_m400", {}, 0.08, 1e-4, 2, 4, 3, 8),
+}
+
+
+@pytest.mark.parametrize("case", list(REPLAY))
+def test_trajectory_replay(case):
+    name, over, std, tie, C, n_per, n_skip, n_burn = REPLAY[case]
+    w = dataclasses.replace(WORKLOADS[name], **over)
     p = stress_params(w, std, 21)
     om = oracle.Model.from_workload(w)
-    C, n_per, n_skip, n_burn, seed = 6, 12, 3, 10, 1234
+    seed = 1234
     init = random_sz0_spins(w.N, C, 8)
     ref, acc_ref, final_ref, ctr_ref, _, log = oracle.exchange_metropolis(
         om, p, init, seed, n_per, n_skip, n_burn, record=True)
@@ -68,7 +87,9 @@ def test_trajectory_replay(name, std, tie):
         assert np.allclose(acc.cpu().numpy(), acc_ref, atol=1e-6)
         bits = ((final_ref > 0) * (1 << np.arange(w.N, dtype=object))).sum(axis=1)
         lo = np.array([int(b) & ((1 << 64) - 1) for b in bits], dtype=np.uint64)
+        hi = np.array([int(b) >> 64 for b in bits], dtype=np.uint64)
         assert (st[:, 0] == lo).all()
+        assert (st[:, 1] == hi).all()
 
 
 def test_auto_nskip_and_continuation():
@@ -91,8 +112,11 @@ def test_auto_nskip_and_continuation():
     assert (s2.cpu().numpy().reshape(C, 4, -1) == ref2.reshape(C, 9, -1)[:, 5:]).all()
 
 
-def test_distribution_matches_exact_4x4():
-    w = dataclasses.replace(WORKLOADS["4x4_fp64_exact"], is_complex=True, n_hidden=8)
+@pytest.mark.parametrize("over", [{"n_hidden": 8},
+                                  {"n_hidden": 8, "n_rbm": 2, "precision": "fp32"}],
+                         ids=["fp64_cache", "fp32_cache_k2"])
+def test_distribution_matches_exact_4x4(over):
+    w = dataclasses.replace(WORKLOADS["4x4_fp64_exact"], is_complex=True, **over)
     p = stress_params(w, 0.25, 1)
     om = oracle.Model.from_workload(w)
     masks, spins = oracle.sector_basis(16)
