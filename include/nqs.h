@@ -153,6 +153,23 @@ nqs_status nqs_logpsi(nqs_ctx* ctx, const int8_t* spins, int64_t S, double* logp
 nqs_status nqs_eloc(nqs_ctx* ctx, const int8_t* spins, int64_t S, double* logpsi_out,
                     double* eloc_out, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): nqs_eloc without
+ * a workspace.  Same results as nqs_eloc (the same kernels); eloc_out and
+ * logpsi_out (optional) as there.  The kernels' per-configuration partials,
+ * (N/2) x 6 doubles each, live in a 64 MiB device array that the library
+ * holds on each GPU it runs on until the process ends, so S is limited to
+ * floor(2^26 / (24 N)) configurations (174762 at 4x4, 77672 at 6x6, 43690 at
+ * 8x8, 27962 at 10x10): larger S returns NQS_ERR_ARG with nothing launched.
+ * Only models with a fused (K*M <= 128) or wide (K*M > 128, FP32 or
+ * split-BF16 theta) E_loc kernel are served; others return NQS_ERR_ARG.  The
+ * context's device must be current.  Allocates nothing, clears nothing (every
+ * partial read is written earlier in the same call) and is asynchronous on
+ * the stream.  Calls that overlap on one GPU (other streams or threads) share
+ * the array and race: order them on one stream. */
+nqs_status nqs_eloc_noalloc(nqs_ctx* ctx, const int8_t* spins, int64_t S, double* logpsi_out,
+                            double* eloc_out, hipStream_t stream);
+
 /* e1 = E_loc and e2 = (H^2 psi)/psi per configuration (two-hop connected
  * configurations), then the FP64 moments and p = 1 Lanczos energy
  * (Sec. 3.3).  For models without the register-resident two-hop kernel

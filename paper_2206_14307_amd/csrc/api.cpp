@@ -312,6 +312,9 @@ nqs_status nqs_create(const nqs_model_desc* d, nqs_ctx** out) {
   c->n_htiles = c->KM / 8;
   c->nk = c->prec == NQS_BF16X2 ? (2 * c->N + 31) / 32 : c->N / 4;
   (void)hipGetDevice(&c->device);
+  // the allocation-free entry point's scratch address on this device (if this
+  // fails, nqs_eloc_noalloc retries and reports the error)
+  (void)noalloc_scratch_init(c->device);
   if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) !=
       hipSuccess)
     c->n_cu = 256;

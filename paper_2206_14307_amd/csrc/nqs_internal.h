@@ -199,5 +199,8 @@ hipError_t launch_moments2(const double* e1e2, const double* e3, const double* l
                            int exact, double* result, hipStream_t st);
 hipError_t launch_grad(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
                        const void* w, void* O_out, hipStream_t st);
+// Resolve the current device's copy of the allocation-free entry point's
+// scratch array (once per device; the device must be current).
+hipError_t noalloc_scratch_init(int device);
 
 }  // namespace nqs

@@ -23,7 +23,7 @@ OP = {"logpsi": 0, "eloc": 1, "moments": 2, "grad": 3, "sr": 4, "sample": 5, "sq
       "moments2": 9}
 
 EXPORTS = ["nqs_create", "nqs_destroy", "nqs_num_params", "nqs_workspace_bytes", "nqs_set_params",
-           "nqs_logpsi", "nqs_eloc", "nqs_lanczos_moments", "nqs_lanczos_moments_p2", "nqs_grad", "nqs_sr_solve",
+           "nqs_logpsi", "nqs_eloc", "nqs_eloc_noalloc", "nqs_lanczos_moments", "nqs_lanczos_moments_p2", "nqs_grad", "nqs_sr_solve",
            "nqs_chain_init", "nqs_sample", "nqs_enumerate_sz0", "nqs_set_factor_form",
            "nqs_structure_factor", "nqs_get_params", "nqs_vmc_step", "nqs_sr_solve_cg",
            "nqs_profile_enable", "nqs_profile_read", "nqs_status_str", "nqs_last_error"]
@@ -81,6 +81,7 @@ def load_library(path: str = LIB_PATH):
         "nqs_set_params": ([vp, vp, vp], C.c_int),
         "nqs_logpsi": ([vp, vp, i64, vp, vp, C.c_size_t, vp], C.c_int),
         "nqs_eloc": ([vp, vp, i64, vp, vp, vp, C.c_size_t, vp], C.c_int),
+        "nqs_eloc_noalloc": ([vp, vp, i64, vp, vp, vp], C.c_int),
         "nqs_lanczos_moments": ([vp, vp, i64, C.c_int, vp, C.POINTER(Moments), vp, C.c_size_t, vp],
                                 C.c_int),
         "nqs_lanczos_moments_p2": ([vp, vp, i64, C.c_int, vp, C.POINTER(Moments2), vp, C.c_size_t,
