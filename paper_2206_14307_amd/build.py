@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libnqs.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "tables.cpp", "lds_layout.cpp", "k_prep.hip", "k_theta.hip", "k_eloc.hip", "k_eloc_reg.hip", "k_eloc_fused.hip", "k_eloc_wide.hip", "k_grad.hip", "k_grad_fused.hip",
+SOURCES = ["api.cpp", "tables.cpp", "lds_layout.cpp", "k_prep.hip", "k_theta.hip", "k_eloc.hip", "k_eloc_reg.hip", "k_eloc_fused.hip", "k_eloc_wide.hip", "k_grad.hip", "k_grad_fused.hip", "k_grad_wide.hip",
            "k_sample.hip", "k_sr.hip", "k_enum.hip", "k_sq.hip", "k_vmc.hip", "k_cg.hip",
            "k_lanczos2.hip", "k_noalloc.hip"]
 ARCH = "gfx950"

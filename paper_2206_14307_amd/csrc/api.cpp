@@ -75,7 +75,8 @@ size_t chunk_bytes_per_sample(const nqs_ctx* c, int op) {
     case NQS_OP_MOMENTS: return z.L + z.w + z.t + z.partial + z.partial2;
     // plus the neighbour row, its log psi and e1, e2
     case NQS_OP_MOMENTS2: return z.L + z.w + z.t + z.partial + z.partial2 + c->N + 48;
-    case NQS_OP_GRAD: return z.L + z.w + z.t;
+    // the wide gradient kernel recomputes tanh(theta): no t buffer
+    case NQS_OP_GRAD: return z.L + z.w + (grad_wide_supported(c) ? 16 : z.t);
     default: return 0;
   }
 }
@@ -164,7 +165,7 @@ Work plan(const nqs_ctx* c, int op, int64_t S, void* ws) {
   wk.L = (double*)cv.take(z.L * ch);
   if (op != NQS_OP_LOGPSI) {
     wk.w = cv.take(z.w * ch);
-    wk.t = cv.take(z.t * ch);
+    if (!(op == NQS_OP_GRAD && grad_wide_supported(c))) wk.t = cv.take(z.t * ch);
   }
   if (op == NQS_OP_ELOC || mom) wk.partial = (double*)cv.take(z.partial * ch);
   if (op == NQS_OP_ELOC || op == NQS_OP_GRAD) wk.lp = (double*)cv.take((size_t)16 * ch);
@@ -791,11 +792,15 @@ nqs_status nqs_grad(nqs_ctx* c, const int8_t* spins, int64_t S, void* O_out, dou
     const int64_t n = std::min(wk.chunk, S - s0);
     const int8_t* sp = spins + s0 * c->N;
     double* lp = logpsi_out ? logpsi_out + 2 * s0 : wk.lp;
-    hipError_t e = NQS_RUN(c, K_THETA, st, launch_theta(c, sp, n, wk.L, wk.t, st));
+    // wide models: theta keeps only the per-image log amplitudes (no tanh in
+    // HBM); the gradient kernel recomputes theta
+    const bool wide = grad_wide_supported(c);
+    hipError_t e = NQS_RUN(c, K_THETA, st, launch_theta(c, sp, n, wk.L, wide ? nullptr : wk.t, st));
     if (e == hipSuccess) e = NQS_RUN(c, K_LSE, st, launch_lse(c, wk.L, n, lp, wk.w, st));
     if (e == hipSuccess)
       e = NQS_RUN(c, K_GRAD, st,
-                  launch_grad(c, sp, n, wk.t, wk.w, (char*)O_out + (size_t)s0 * osz, st));
+                  wide ? launch_grad_wide(c, sp, n, wk.w, (char*)O_out + (size_t)s0 * osz, st)
+                       : launch_grad(c, sp, n, wk.t, wk.w, (char*)O_out + (size_t)s0 * osz, st));
     if (e != hipSuccess) return hip_fail(c, e, "grad launch");
   }
   return NQS_OK;

@@ -199,6 +199,11 @@ hipError_t launch_moments2(const double* e1e2, const double* e3, const double* l
                            int exact, double* result, hipStream_t st);
 hipError_t launch_grad(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
                        const void* w, void* O_out, hipStream_t st);
+// O_k for K*M > 128 (FP32 / split-BF16 theta) from the normalised image
+// weights w [S][K][G] (complex float) of launch_lse, theta recomputed in-kernel.
+bool grad_wide_supported(const nqs_ctx* c);
+hipError_t launch_grad_wide(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* w,
+                            void* O_out, hipStream_t st);
 // Resolve the current device's copy of the allocation-free entry point's
 // scratch array (once per device; the device must be current).
 hipError_t noalloc_scratch_init(int device);

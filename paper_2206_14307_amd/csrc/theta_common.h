@@ -201,6 +201,20 @@ __device__ __forceinline__ R logcosh_step(R x, R y, R& pr, R& pi, uint32_t& par,
   return ax;
 }
 
+// tanh(x + i y) alone, by the identity above (tanh has period i pi, so the
+// reduced angle r suffices): (sgn(x)(1 - e^2) + i 4 e sin r cos r) / |c|^2.
+__device__ __forceinline__ void tanh_c(float x, float y, float& tr, float& ti) {
+  const float e = exp_t(-2.f * fabsf(x));
+  float sn, cs;
+  uint32_t par = 0u;
+  sincos_pi(y, sn, cs, par);
+  const float d = fmaf(e + e, fmaf(cs, cs, -(sn * sn)), fmaf(e, e, 1.f));   // |c|^2
+  const float inv = rcp_t(d);
+  const float tu = fmaf(-e, e, 1.f) * inv;
+  tr = x < 0.f ? -tu : tu;
+  ti = (4.f * e) * (sn * cs) * inv;
+}
+
 // Apply the collected (-1)^k of the epilogue to a product.
 template <typename R>
 __device__ __forceinline__ void apply_parity(R& pr, R& pi, uint32_t par) {

@@ -2,7 +2,9 @@
 
 Models with K*M <= 128 in FP32 or split-BF16 theta take the fused gradient
 kernel (theta, weights and the image contraction in one pass, nothing of
-size S x G x K*M in HBM); the rest take the materialised path.  Each case
+size S x G x K*M in HBM); wider FP32 / split-BF16 models take the wide
+gradient kernel (image weights from a log-amplitude pass, theta recomputed
+in-kernel); FP64 models the materialised path.  Each case
 compares every O row with the oracle's gradient, per row ||dO|| / ||O||,
 and the log psi that nqs_grad also returns.  Cases: drawn parameters and
 stress parameters (std 0.3, complex, B1 at K = (pi, pi)), one and two RBMs,
@@ -43,6 +45,15 @@ CASES = {
     "4x4_m16_fp32": ("4x4_fp64_exact", {"precision": "fp32", "is_complex": True}, 0.2),
     "4x4_k2_m8_nobias": ("4x4_fp64_exact", {"precision": "fp32", "is_complex": True,
                                             "n_rbm": 2, "n_hidden": 8, "use_bias": False}, 0.2),
+    # K*M > 128: theta (log amplitudes only) + log-sum-exp, then the wide
+    # gradient kernel with theta recomputed in-kernel
+    "8x8_k4_m256_fp32": ("8x8_k4_m256", {"precision": "fp32"}, None),
+    "8x8_k4_m256_bf16x2": ("8x8_k4_m256", {}, None),
+    "10x10_m400_bf16x2_std0.05": ("10x10_m400", {}, 0.05),
+    "10x10_m400_fp32": ("10x10_m400", {"precision": "fp32"}, None),
+    "6x6_m144_b1_pi": ("6x6_fp32_eloc", {"n_hidden": 144, "irrep": "B1", "kx": 3, "ky": 3}, 0.1),
+    "6x6_k2_m128_nobias_bf16x2": ("6x6_fp32_eloc", {"n_rbm": 2, "n_hidden": 128, "use_bias": False,
+                                                    "precision": "bf16x2"}, 0.05),
 }
 
 

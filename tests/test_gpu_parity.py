@@ -294,6 +294,25 @@ def test_eloc_both_factor_forms(name, case):
     assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp)) < tol
 
 
+@pytest.mark.parametrize("case", ["std2e-3", "flat_column"])
+@pytest.mark.parametrize("name,over", [("8x8_k4_m256", {"precision": "fp32"}),
+                                       ("10x10_m400", {})])
+def test_wide_eloc_small_and_vanishing_exchange_factors(name, over, case):
+    """The wide kernel's products s + t T at |T| ~ 3e-3 (std 2e-3: every chunk
+    of 8 units multiplies factors within 1e-5 of s) and with one hidden unit
+    whose W column is flat (T = 0 on every bond), against the oracle."""
+    w = dataclasses.replace(WORKLOADS[name], **over)
+    om = oracle.Model.from_workload(w)
+    p = _flat_column(draw_params(w), w, 5) if case == "flat_column" else \
+        stress_params(w, float(case[3:]), 12)
+    sp = random_sz0_spins(w.N, 7, 5)
+    m = make(w, p)
+    glp, gel = m.eloc(cuda(sp))
+    tol = TOL[w.precision]
+    assert max_logpsi_err(glp.cpu().numpy(), oracle.logpsi(om, p, sp)) < tol
+    assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp)) < tol
+
+
 # ----------------------------------------------- wide hidden layers (K*M > 128)
 
 def _neel_and_stripe(L):
