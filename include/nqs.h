@@ -56,7 +56,11 @@ typedef enum {
 
 typedef enum {
     NQS_FP64 = 0,    /* everything in FP64 (theta GEMM on FP64 MFMA) */
-    NQS_FP32 = 1,    /* FP32 arithmetic, theta GEMM on FP32 MFMA */
+    NQS_FP32 = 1,    /* FP32 arithmetic; the theta GEMM and the gradient contraction
+                        have FP32 numerics (exact products, FP32 accumulation) and run
+                        on BF16 MFMA from an exact three-term BF16 split of the FP32
+                        operand where that is faster (x = +-1/2 is exact in BF16),
+                        else on FP32 MFMA */
     NQS_BF16X2 = 2   /* theta GEMM on BF16 MFMA with W split into hi + lo BF16 parts,
                         FP32 accumulation; everything else as NQS_FP32 */
 } nqs_precision;

@@ -155,4 +155,31 @@ __device__ __forceinline__ void wave_sync_lds() {
 
 __device__ __forceinline__ int spin_at(const int8_t* row, int i) { return (int)row[i]; }
 
+// Upper halves (BF16 bit patterns) of two FP32 bit patterns, a in the low half.
+__device__ __forceinline__ uint32_t pack_hi16(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_perm(b, a, 0x07060302u);
+}
+
+// Exact three-term BF16 split of four FP32 values for the K slots of a
+// 16x16x32 BF16 MFMA operand: hi = v with its low 16 bits cleared, mid the
+// same of v - hi, lo = v - hi - mid (at most 8 significant bits, so exact in
+// BF16); hi + mid + lo == v.  o1 = (hi_0..3, mid_0..3), o2 = (lo_0..3, 0 x 4).
+// Against an exact BF16 partner (here +-1/2 or 1) every product is the exact
+// FP32 product, so only the FP32 accumulation rounds.
+__device__ __forceinline__ void split3_bf16(const float (&v)[4], bf16x8& o1, bf16x8& o2) {
+  uint32_t hb[4], mb[4], lb[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    hb[r] = __float_as_uint(v[r]);
+    const float r1 = v[r] - __uint_as_float(hb[r] & 0xffff0000u);      // exact
+    mb[r] = __float_as_uint(r1);
+    lb[r] = __float_as_uint(r1 - __uint_as_float(mb[r] & 0xffff0000u)); // exact
+  }
+  const uint32_t w1[4] = {pack_hi16(hb[0], hb[1]), pack_hi16(hb[2], hb[3]),
+                          pack_hi16(mb[0], mb[1]), pack_hi16(mb[2], mb[3])};
+  const uint32_t w2[4] = {pack_hi16(lb[0], lb[1]), pack_hi16(lb[2], lb[3]), 0u, 0u};
+  o1 = __builtin_bit_cast(bf16x8, w1);
+  o2 = __builtin_bit_cast(bf16x8, w2);
+}
+
 }  // namespace nqs

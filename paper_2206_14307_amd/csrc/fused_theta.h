@@ -57,7 +57,7 @@ __device__ __forceinline__ void theta_block(
     // a . (g sigma): FP32 / FP64 fragments hold x_j for j = q mod 4
     R xr = R(0), xi = R(0);
     const R* ak = avec + (size_t)k * N * 2;
-    if constexpr (PREC != NQS_BF16X2) {
+    if constexpr (!bf16_mfma(PREC)) {
 #pragma unroll
       for (int kk = 0; kk < NK; ++kk) {
         xr = fmaf_t(bx[kk], ak[2 * (4 * kk + q)], xr);

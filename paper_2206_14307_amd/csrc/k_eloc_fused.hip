@@ -333,7 +333,9 @@ hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, d
   int64_t blocks = (items + kFusedWaves - 1) / kFusedWaves;
   blocks = std::min<int64_t>(blocks, c->n_cu > 0 ? c->n_cu : 256);
   eloc_fused_kernel<N, PREC, K, M, RECIP><<<(unsigned)blocks, 64 * kFusedWaves, 0, st>>>(
-      spins, S, c->dev.perm, c->G, (const typename T::AFrag*)c->par.wfrag, (const R*)c->par.bias,
+      spins, S, c->dev.perm, c->G,
+      (const typename T::AFrag*)(PREC == kPrecF32X3 ? c->par.wfrag3 : c->par.wfrag),
+      (const R*)c->par.bias,
       (const R*)c->par.avec, c->dev.bonds, c->dev.fmap, c->dev.frow, c->dev.chi,
       (const R*)(RECIP ? c->par.Urec : c->par.Tdir), part);
   hipError_t e = hipGetLastError();
@@ -366,7 +368,12 @@ hipError_t run_prec(const nqs_ctx* c, const int8_t* spins, int64_t S, double* pa
                     double* logpsi, double* eloc, int es, hipStream_t st) {
   switch (c->prec) {
     case NQS_FP64: return run_if_fits<N, NQS_FP64, K, M>(c, spins, S, part, logpsi, eloc, es, st);
-    case NQS_FP32: return run_if_fits<N, NQS_FP32, K, M>(c, spins, S, part, logpsi, eloc, es, st);
+    case NQS_FP32:
+      // theta from the three-term BF16 split of W where its fragments fit in LDS
+      if constexpr (FusedCfg<N, kPrecF32X3, K, M, false>::LDS <= kLdsLimit)
+        return run_if_fits<N, kPrecF32X3, K, M>(c, spins, S, part, logpsi, eloc, es, st);
+      else
+        return run_if_fits<N, NQS_FP32, K, M>(c, spins, S, part, logpsi, eloc, es, st);
     default: return run_if_fits<N, NQS_BF16X2, K, M>(c, spins, S, part, logpsi, eloc, es, st);
   }
 }

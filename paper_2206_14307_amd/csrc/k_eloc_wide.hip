@@ -345,7 +345,8 @@ template <int N, int PREC>
 hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, hipStream_t st,
                const int16_t* parent = nullptr) {
   const int64_t blocks = std::min<int64_t>(S, c->n_cu > 0 ? c->n_cu : 256);
-  const auto* wf = (const typename ThetaTraits<PREC>::AFrag*)c->par.wfrag;
+  const auto* wf = (const typename ThetaTraits<PREC>::AFrag*)(PREC == kPrecF32X3 ? c->par.wfrag3
+                                                                                 : c->par.wfrag);
   if (parent)
     eloc_wide_kernel<N, PREC, true><<<(unsigned)blocks, 64 * kWideWaves, 0, st>>>(
         spins, S, c->dev.perm, c->G, c->K, c->M, wf, (const float*)c->par.bias,
@@ -377,11 +378,11 @@ hipError_t launch_eloc_wide_pairs(const nqs_ctx* c, const int8_t* spins, int64_t
   const bool bf = c->prec == NQS_BF16X2;
   switch (c->N) {
     case 36: return bf ? run<36, NQS_BF16X2>(c, spins, S, part, st, parent)
-                       : run<36, NQS_FP32>(c, spins, S, part, st, parent);
+                       : run<36, kPrecF32X3>(c, spins, S, part, st, parent);
     case 64: return bf ? run<64, NQS_BF16X2>(c, spins, S, part, st, parent)
-                       : run<64, NQS_FP32>(c, spins, S, part, st, parent);
+                       : run<64, kPrecF32X3>(c, spins, S, part, st, parent);
     case 100: return bf ? run<100, NQS_BF16X2>(c, spins, S, part, st, parent)
-                        : run<100, NQS_FP32>(c, spins, S, part, st, parent);
+                        : run<100, kPrecF32X3>(c, spins, S, part, st, parent);
     default: return hipErrorNotSupported;
   }
 }

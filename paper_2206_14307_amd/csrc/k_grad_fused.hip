@@ -13,11 +13,17 @@
 // fused E_loc kernel); the weights use a running maximum m of Re L over the
 // blocks seen so far (the accumulators are rescaled by e^{m_old - m_new}
 // when it grows).  The products u t go through a 16 x 16 LDS tile per hidden
-// tile into the B operand of a second 16x16x4 FP32 MFMA contraction over the
-// images, whose A operand is the gathered image x with an extra all-ones row:
+// tile into the B operand of a second MFMA contraction over the images, whose
+// A operand is the gathered image x with an extra all-ones row:
 //   C[j][col] = sum_g A[j][g] B[g][col],  A = [x_g | 1],  B = [Re u t | Im u t | u],
-// so the ones row gives O_b and D, and the u columns give O_a.  Nothing of
-// size S x G x K*M reaches HBM: the traffic is the spin rows and O itself.
+// so the ones row gives O_b and D, and the u columns give O_a.  The
+// contraction runs on 16x16x32 BF16 MFMA with each FP32 value of B split
+// exactly into three BF16 terms (split3_bf16; x = +-1/2 and 1 are exact in
+// BF16), so its products are the FP32 products and only the FP32
+// accumulation rounds: lane (q, c) supplies images 4q .. 4q+3 (hi and mid in
+// one MFMA, lo in a second), and the A operand is x of those images at site
+// 16 st + c, staged twice over in one 16-byte LDS word per (q, site).
+// Nothing of size S x G x K*M reaches HBM: the traffic is the spin rows and O.
 #include "fused_theta.h"
 
 namespace nqs {
@@ -34,11 +40,14 @@ struct GradCfg {
   static constexpr int NCT = NHT + 1;            // + the u tile (2K columns)
   static constexpr int NST = (N + 1 + 15) / 16;  // site tiles incl. the ones row
   static constexpr int NK = nk_of<N, PREC>();
-  static constexpr int TS = 16 * 17;             // one padded 16 x 16 transpose tile
-  static constexpr int XS = 16 * NST;            // row of the image tile: sites + ones + zeros
+  // one 16 x 16 tile, rows (images) 20 floats apart: the contraction's reads
+  // of rows 4q + r by the four lane groups q fall on disjoint bank groups
+  static constexpr int TR = 20;
+  static constexpr int TS = 16 * TR;
+  static constexpr int XQ = 4 * 16 * NST;        // image words: [q][site] incl. ones + zeros
   static constexpr size_t LDS = (size_t)NHT * NK * 64 * sizeof(typename T::AFrag) +
                                 (size_t)kGradWaves * NCT * TS * sizeof(float) +
-                                (size_t)kGradWaves * 16 * XS * sizeof(float) +
+                                (size_t)kGradWaves * XQ * 16 +
                                 (size_t)(2 * KM + 2 * K * N) * sizeof(float);
 };
 
@@ -58,11 +67,12 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
   using T = ThetaTraits<PREC>;
   using AF = typename T::AFrag;
   constexpr int NHT = Cfg::NHT, NCT = Cfg::NCT, NST = Cfg::NST, NK = Cfg::NK, TS = Cfg::TS;
-  constexpr int XS = Cfg::XS;
+  constexpr int TR = Cfg::TR, XQ = Cfg::XQ;
   constexpr int TPR = M / 8;
   __shared__ __align__(16) AF Wl[NHT * NK * 64];
   __shared__ float tb[kGradWaves][NCT * TS];
-  __shared__ float xb[kGradWaves][16 * XS];          // the block's images x_g (rows), sites (columns)
+  // the block's images as BF16 words [q][site]: x of images 4q .. 4q+3, twice
+  __shared__ __align__(16) uint4 xq[kGradWaves][XQ];
   __shared__ float bl[2 * Cfg::KM], al[2 * K * N];   // hidden and visible biases
 
   for (int idx = threadIdx.x; idx < NHT * NK * 64; idx += blockDim.x) Wl[idx] = wfrag[idx];
@@ -71,9 +81,12 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
   const int lane0 = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float* tw = tb[wv];
   for (int idx = lane0; idx < TS; idx += 64) tw[NHT * TS + idx] = 0.f;   // unused u columns
-  float* xw = xb[wv];
-  for (int idx = lane0; idx < 16 * (XS - N); idx += 64)                   // ones row, zero pad
-    xw[(idx / (XS - N)) * XS + N + idx % (XS - N)] = idx % (XS - N) == 0 ? 1.f : 0.f;
+  uint4* xw = xq[wv];
+  for (int idx = lane0; idx < 4 * (16 * NST - N); idx += 64) {            // ones row, zero pad
+    const int qq = idx / (16 * NST - N), j = N + idx % (16 * NST - N);
+    const uint32_t one = j == N ? 0x3F803F80u : 0u;                         // BF16 1.0, twice
+    xw[qq * 16 * NST + j] = make_uint4(one, one, one, one);
+  }
   __syncthreads();
 
   const int nblk = G / 16;
@@ -97,18 +110,32 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
       const uint8_t* prow = perm + (size_t)g * N;
       typename T::BFrag bx[NK];
       load_bfrag<N, PREC>(srow, prow, q, bx);
-      // the images as rows of the contraction's A operand (sites x images)
-      if constexpr (PREC == NQS_BF16X2) {
+      // image c into the contraction's A words: BF16 x at slots c % 4 and c % 4 + 4
+      // of word (c / 4, site)
+      unsigned short* xh = reinterpret_cast<unsigned short*>(xw) + (c >> 2) * 16 * NST * 8 + (c & 3);
+      if constexpr (bf16_mfma(PREC)) {
 #pragma unroll
-        for (int kk = 0; kk < NK; ++kk)
+        for (int kk = 0; kk < NK; ++kk) {
+          // the fragment's BF16 pairs as words, halves taken with integer shifts
+          const uint4 wb = __builtin_bit_cast(uint4, bx[kk]);
+          const uint32_t wd[4] = {wb.x, wb.y, wb.z, wb.w};
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             const int kap = 32 * kk + 8 * q + e;
-            if (kap < N) xw[c * XS + kap] = (float)bx[kk][e];
+            if (kap < N) {
+              const unsigned short h = (unsigned short)(wd[e >> 1] >> (16 * (e & 1)));
+              xh[kap * 8] = h;
+              xh[kap * 8 + 4] = h;
+            }
           }
+        }
       } else {
 #pragma unroll
-        for (int kk = 0; kk < NK; ++kk) xw[c * XS + 4 * kk + q] = (float)bx[kk];
+        for (int kk = 0; kk < NK; ++kk) {
+          const unsigned short h = (unsigned short)(__float_as_uint((float)bx[kk]) >> 16);
+          xh[(4 * kk + q) * 8] = h;
+          xh[(4 * kk + q) * 8 + 4] = h;
+        }
       }
       float tr[NHT * 2], ti[NHT * 2], Pr[K], Pi[K], Ai[K];
       double Er[K];
@@ -142,7 +169,7 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
 #pragma unroll
       for (int ht = 0; ht < NHT; ++ht) {
         const int k = ht / TPR;
-        float* row = tw + ht * TS + c * 17;
+        float* row = tw + ht * TS + c * TR;
 #pragma unroll
         for (int u2 = 0; u2 < 2; ++u2) {
           const float a = tr[2 * ht + u2], b = ti[2 * ht + u2];
@@ -153,24 +180,25 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
       if (q == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          tw[NHT * TS + c * 17 + 2 * k] = ur[k];
-          tw[NHT * TS + c * 17 + 2 * k + 1] = ui[k];
+          tw[NHT * TS + c * TR + 2 * k] = ur[k];
+          tw[NHT * TS + c * TR + 2 * k + 1] = ui[k];
         }
       }
       wave_sync_lds();
-      // contraction over the block's images, 4 per MFMA step: images 4r + q
-      const float* xl = xw + q * XS + c;
-#pragma unroll 1
-      for (int r = 0; r < 4; ++r) {
-        float a[NST];
+      // contraction over the block's images: lane (q, c) supplies images
+      // 4q .. 4q+3 of column c (split into BF16 terms) and of site 16 st + c
 #pragma unroll
-        for (int st = 0; st < NST; ++st) a[st] = xl[4 * r * XS + 16 * st];
+      for (int ct = 0; ct < NCT; ++ct) {
+        float v[4];
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-          const float b = tw[ct * TS + (4 * r + q) * 17 + c];
+        for (int r = 0; r < 4; ++r) v[r] = tw[ct * TS + (4 * q + r) * TR + c];
+        bf16x8 b1, b2;
+        split3_bf16(v, b1, b2);
 #pragma unroll
-          for (int st = 0; st < NST; ++st)
-            acc[st][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], b, acc[st][ct], 0, 0, 0);
+        for (int st = 0; st < NST; ++st) {
+          const bf16x8 ax = __builtin_bit_cast(bf16x8, xw[q * 16 * NST + 16 * st + c]);
+          acc[st][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b1, acc[st][ct], 0, 0, 0);
+          acc[st][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, b2, acc[st][ct], 0, 0, 0);
         }
       }
       wave_sync_lds();
@@ -264,6 +292,9 @@ hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, void* O, double
 template <int N, int K, int M>
 hipError_t run_prec(const nqs_ctx* c, const int8_t* spins, int64_t S, void* O, double* logpsi,
                     hipStream_t st) {
+  // theta of FP32 models stays on FP32 MFMA here: the three-term BF16 form
+  // (larger W fragments in LDS) measured slower in this kernel, 24.2 ms
+  // against 20.3 ms at 6x6 M = 72
   return c->prec == NQS_FP32 ? run<N, NQS_FP32, K, M>(c, spins, S, O, logpsi, st)
                              : run<N, NQS_BF16X2, K, M>(c, spins, S, O, logpsi, st);
 }

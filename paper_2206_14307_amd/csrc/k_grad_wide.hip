@@ -1,6 +1,6 @@
 // Log-derivatives O_k = d log psi / d theta_k (Sec. 3.2, below Eq. (12)) for
 // models whose hidden layer does not fit one wavefront (K*M > 128), theta in
-// FP32 or split BF16.
+// FP32 (on BF16 MFMA from the exact three-term split of W) or split BF16.
 //
 // With the normalised image weights w_kg = chi_g psi_s^(k)(g sigma)/psi(sigma)
 // (written by the log-sum-exp kernel after a theta pass that keeps only the
@@ -14,8 +14,9 @@
 // W) plus, with biases, one item for O_a; wavefront w takes items w, w + kGW,
 // ... in rounds.  All wavefronts walk the G/16 image blocks in lockstep, so
 // the block's images are staged once in LDS for all of them (double-buffered,
-// one barrier per block): as FP32 +-1/2 rows [image][site | 1 | 0...] and, for
-// split BF16, as [x | x | 0] rows.  Per block a tile item
+// one barrier per block): as BF16 rows [x | x | 0] (split BF16) or
+// [x | x | x | 0] (FP32), and as the contraction's words below.  Per block a
+// tile item
 //   * computes theta^T = X W^T on MFMA (the image rows as the A operand, the W
 //     fragments of the tile, kept in registers for the whole item, as the B
 //     operand): lane (q, c) = (lane/16, lane%16) receives row c of the tile
@@ -25,9 +26,16 @@
 //     multiplies by w; a second exchange leaves lane c with component c & 1
 //     of w t for all four images -- which is already the A-operand layout of
 //     the contraction with the images taken in the order 4q + r at step r;
-//   * accumulates C[row][site] += sum_g (w t)[row][g] x[g][site] on 16x16x4
-//     FP32 MFMA, the B operand read from the staged FP32 rows (the column of
-//     ones at site N gives O_b).
+//   * accumulates C[row][site] += sum_g (w t)[row][g] x[g][site] on 16x16x32
+//     BF16 MFMA: each FP32 value v of w t is split exactly into three BF16
+//     terms (hi = v with its low 16 bits cleared, mid the same of v - hi, lo =
+//     v - hi - mid, which has at most 8 significant bits), and x = +-1/2 is
+//     exact in BF16, so every product is the exact FP32 product and only the
+//     FP32 accumulation rounds -- at a quarter of the MFMA time of 16x16x4
+//     FP32.  Lane (q, c) puts hi and mid of its four images in the K slots of
+//     one MFMA and lo in a second; the B operand is x of images 4q .. 4q+3 at
+//     site 16 sb + c, staged twice over in one 16-byte LDS word per (q, site)
+//     (the column of ones at site N gives O_b).
 // The O_a item multiplies rows of w instead of w t.  Each lane then writes
 // units 8 ht + 2q, 8 ht + 2q + 1 at sites 16 sb + c: 16 consecutive complex
 // values per row of lanes.
@@ -43,9 +51,10 @@ template <int N, int PREC>
 struct GradWideCfg {
   static constexpr int NK = nk_of<N, PREC>();
   static constexpr int NSB = (N + 1 + 15) / 16;      // site blocks incl. the ones column
-  static constexpr int XS = 16 * NSB + 4;            // FP32 row stride (conflict-free reads)
+  static constexpr int XS = 16 * NSB + 4;            // FP32 theta rows (conflict-free reads)
   static constexpr int XB = 32 * NK + 8;             // BF16 row stride (elements)
-  static constexpr bool BF = PREC == NQS_BF16X2;
+  static constexpr bool BF = bf16_mfma(PREC);         // theta on BF16 MFMA
+  static constexpr int XC = x_copies(PREC);           // copies of x along its K axis
 };
 
 __device__ __forceinline__ float swap_adjacent(float v) {   // value of lane l ^ 1
@@ -53,7 +62,7 @@ __device__ __forceinline__ float swap_adjacent(float v) {   // value of lane l ^
 }
 
 template <int N, int PREC>
-__global__ __launch_bounds__(64 * kGW) void grad_wide_kernel(
+__global__ __launch_bounds__(64 * kGW) __attribute__((amdgpu_waves_per_eu(4))) void grad_wide_kernel(
     const int8_t* __restrict__ spins, int64_t S, const uint8_t* __restrict__ perm, int G, int K,
     int M, int use_bias, int Prbm, int64_t P,
     const typename ThetaTraits<PREC>::AFrag* __restrict__ wfrag, const float* __restrict__ bias,
@@ -61,8 +70,11 @@ __global__ __launch_bounds__(64 * kGW) void grad_wide_kernel(
   using Cfg = GradWideCfg<N, PREC>;
   using T = ThetaTraits<PREC>;
   constexpr int NK = Cfg::NK, NSB = Cfg::NSB, XS = Cfg::XS, XB = Cfg::XB;
-  __shared__ __align__(16) float xt[2][16 * XS];
+  __shared__ __align__(16) float xt[Cfg::BF ? 1 : 2][Cfg::BF ? 4 : 16 * XS];
   __shared__ __align__(16) unsigned short xb[Cfg::BF ? 2 : 1][Cfg::BF ? 16 * XB : 8];
+  // [q][site]: BF16 x of images 4q .. 4q+3, twice (16 lanes of one q read 16
+  // consecutive words: no bank conflicts)
+  __shared__ __align__(16) uint4 xq[2][4 * 16 * NSB];
   extern __shared__ __align__(16) float wl[];          // [K][G] complex: this configuration's w
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -72,18 +84,20 @@ __global__ __launch_bounds__(64 * kGW) void grad_wide_kernel(
   const int n_items = n_ht + (use_bias ? 1 : 0);
   const int rounds = (n_items + kGW - 1) / kGW;
 
-  // constant parts of the staged rows: site N is 1 (O_b), sites beyond are 0;
-  // the split-BF16 rows are zero beyond position 2N
-  for (int e = tid; e < 2 * 16 * (16 * NSB - N); e += 64 * kGW) {
-    const int b = e / (16 * (16 * NSB - N)), r = e % (16 * (16 * NSB - N));
-    const int ii = r / (16 * NSB - N), j = N + r % (16 * NSB - N);
-    xt[b][ii * XS + j] = j == N ? 1.f : 0.f;
+  // constant parts of the staged operands: in the contraction's, site N is 1
+  // (O_b) and the sites beyond are 0; the split-BF16 theta rows are zero
+  // beyond position 2N
+  for (int e = tid; e < 2 * 4 * (16 * NSB - N); e += 64 * kGW) {
+    const int b = e / (4 * (16 * NSB - N)), r = e % (4 * (16 * NSB - N));
+    const int j = N + r / 4;
+    const uint32_t one = j == N ? 0x3F803F80u : 0u;                 // BF16 1.0, twice
+    xq[b][(r % 4) * 16 * NSB + j] = make_uint4(one, one, one, one);
   }
-  constexpr int PADB = 32 * NK - 2 * N;                // zero K positions of a BF16 row
+  constexpr int PADB = 32 * NK - Cfg::XC * N;          // zero K positions of a BF16 row
   if constexpr (Cfg::BF && PADB > 0) {
     for (int e = tid; e < 2 * 16 * PADB; e += 64 * kGW) {
       const int b = e / (16 * PADB), r = e % (16 * PADB);
-      xb[b][(r / PADB) * XB + 2 * N + r % PADB] = 0;
+      xb[b][(r / PADB) * XB + Cfg::XC * N + r % PADB] = 0;
     }
   }
 
@@ -92,17 +106,26 @@ __global__ __launch_bounds__(64 * kGW) void grad_wide_kernel(
     __syncthreads();                                   // previous configuration done with wl / rows
     const float* ws = w + (size_t)s * K * G * 2;
     for (int e = tid; e < 2 * K * G; e += 64 * kGW) wl[e] = ws[e];
-    // stage the images of block blk into buffer b
+    // stage the images of block blk into buffer b: thread item (site j, image
+    // group qq) reads images 16 blk + 4 qq + r, r = 0..3
     auto stage = [&](int blk, int b) {
-      for (int e = tid; e < 16 * N; e += 64 * kGW) {
-        const int ii = e / N, j = e - ii * N;
-        const int v = srow[perm[(size_t)(blk * 16 + ii) * N + j]];
-        xt[b][ii * XS + j] = v > 0 ? 0.5f : -0.5f;
-        if constexpr (Cfg::BF) {
-          const unsigned short h = v > 0 ? 0x3F00 : 0xBF00;   // BF16 +-1/2
-          xb[b][ii * XB + j] = h;
-          xb[b][ii * XB + N + j] = h;
+      for (int e = tid; e < 4 * N; e += 64 * kGW) {
+        const int qq = e / N, j = e - qq * N;
+        uint32_t h[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ii = 4 * qq + r;
+          const int v = srow[perm[(size_t)(blk * 16 + ii) * N + j]];
+          h[r] = v > 0 ? 0x3F00u : 0xBF00u;                        // BF16 +-1/2
+          if constexpr (Cfg::BF) {
+#pragma unroll
+            for (int cp = 0; cp < Cfg::XC; ++cp) xb[b][ii * XB + cp * N + j] = (unsigned short)h[r];
+          } else {
+            xt[b][ii * XS + j] = v > 0 ? 0.5f : -0.5f;
+          }
         }
+        const uint32_t lo = h[0] | (h[1] << 16), hi = h[2] | (h[3] << 16);
+        xq[b][qq * 16 * NSB + j] = make_uint4(lo, hi, lo, hi);
       }
     };
     stage(0, 0);
@@ -127,7 +150,7 @@ __global__ __launch_bounds__(64 * kGW) void grad_wide_kernel(
         // stage the next block (the next round starts again at block 0)
         if (blk + 1 < nblk) stage(blk + 1, cur ^ 1);
         else if (rd + 1 < rounds) stage(0, cur ^ 1);
-        const float* xc = xt[cur];
+        const float* xc = xt[Cfg::BF ? 0 : cur];
         float A[4];
         if (is_tile) {
           f32x4 th = f32x4{b0, b0, b0, b0};
@@ -172,12 +195,13 @@ __global__ __launch_bounds__(64 * kGW) void grad_wide_kernel(
           }
         }
         if (is_tile || is_a) {
+          bf16x8 a1, a2;
+          split3_bf16(A, a1, a2);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-#pragma unroll
-            for (int sb = 0; sb < NSB; ++sb)
-              acc[sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], xc[(4 * q + r) * XS + 16 * sb + c],
-                                                             acc[sb], 0, 0, 0);
+          for (int sb = 0; sb < NSB; ++sb) {
+            const bf16x8 bx = __builtin_bit_cast(bf16x8, xq[cur][q * 16 * NSB + 16 * sb + c]);
+            acc[sb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bx, acc[sb], 0, 0, 0);
+            acc[sb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, bx, acc[sb], 0, 0, 0);
           }
         }
         __syncthreads();
@@ -221,7 +245,9 @@ hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, const float* w,
   const int64_t blocks = std::min<int64_t>(S, (int64_t)(c->n_cu > 0 ? c->n_cu : 256) * 8);
   grad_wide_kernel<N, PREC><<<(unsigned)blocks, 64 * kGW, lds, st>>>(
       spins, S, c->dev.perm, c->G, c->K, c->M, c->d.use_bias, c->P_rbm, c->P,
-      (const typename ThetaTraits<PREC>::AFrag*)c->par.wfrag, (const float*)c->par.bias, w,
+      (const typename ThetaTraits<PREC>::AFrag*)(PREC == kPrecF32X3 ? c->par.wfrag3
+                                                                    : c->par.wfrag),
+      (const float*)c->par.bias, w,
       (float*)O);
   return hipGetLastError();
 }
@@ -242,11 +268,11 @@ hipError_t launch_grad_wide(const nqs_ctx* c, const int8_t* spins, int64_t S, co
   const float* wf = (const float*)w;
   switch (c->N) {
     case 36: return bf ? run<36, NQS_BF16X2>(c, spins, S, wf, O, st)
-                       : run<36, NQS_FP32>(c, spins, S, wf, O, st);
+                       : run<36, kPrecF32X3>(c, spins, S, wf, O, st);
     case 64: return bf ? run<64, NQS_BF16X2>(c, spins, S, wf, O, st)
-                       : run<64, NQS_FP32>(c, spins, S, wf, O, st);
+                       : run<64, kPrecF32X3>(c, spins, S, wf, O, st);
     case 100: return bf ? run<100, NQS_BF16X2>(c, spins, S, wf, O, st)
-                        : run<100, NQS_FP32>(c, spins, S, wf, O, st);
+                        : run<100, kPrecF32X3>(c, spins, S, wf, O, st);
     default: return hipErrorNotSupported;
   }
 }

@@ -86,6 +86,32 @@ __global__ void prep_wfrag_bf16_kernel(const double2* p, int Prbm, int M, int N,
   }
 }
 
+// FP32 models: fragments of [W_hi | W_mid | W_lo | 0] along the K axis for
+// the three-term BF16 form of theta (hi = the FP32 W with its low 16 bits
+// cleared, mid the same of W - hi, lo = W - hi - mid, exact in BF16).
+__global__ void prep_wfrag_x3_kernel(const double2* p, int Prbm, int M, int N, int n_htiles,
+                                     int nk3, unsigned short* out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)n_htiles * nk3 * 64;
+  if (idx >= total) return;
+  const int l = idx % 64, kk = (idx / 64) % nk3, ht = idx / (64 * nk3);
+  const int row = 16 * ht + (l % 16);
+  for (int e = 0; e < 8; ++e) {
+    const int kap = 32 * kk + 8 * (l / 16) + e;
+    unsigned short v = 0;
+    if (kap < 3 * N) {
+      const double2 w = Wval(p, Prbm, M, N, row / 2, kap % N);
+      const float wf = (float)((row & 1) ? w.y : w.x);
+      const float hi = __uint_as_float(__float_as_uint(wf) & 0xffff0000u);
+      const float r1 = wf - hi;
+      const float mid = __uint_as_float(__float_as_uint(r1) & 0xffff0000u);
+      const float part = kap < N ? hi : kap < 2 * N ? mid : r1 - mid;
+      v = (unsigned short)(__float_as_uint(part) >> 16);
+    }
+    out[idx * 8 + e] = v;
+  }
+}
+
 template <typename R>
 __global__ void prep_bias_kernel(const double2* p, int Prbm, int K, int M, int N, int use_bias,
                                  R* bias, R* avec) {
@@ -315,6 +341,12 @@ hipError_t prep_typed(const nqs_ctx* c, hipStream_t st) {
   } else {
     prep_wfrag_kernel<R><<<(nfrag + 255) / 256, 256, 0, st>>>(p, c->P_rbm, c->M, c->N,
                                                                c->n_htiles, c->nk, (R*)c->par.wfrag);
+  }
+  if (c->par.wfrag3) {
+    const int nk3 = (3 * c->N + 31) / 32;
+    const int64_t nf3 = (int64_t)c->n_htiles * nk3 * 64;
+    prep_wfrag_x3_kernel<<<(nf3 + 255) / 256, 256, 0, st>>>(
+        p, c->P_rbm, c->M, c->N, c->n_htiles, nk3, (unsigned short*)c->par.wfrag3);
   }
   const int nb = (std::max(c->K * c->M, c->K * c->N) + 255) / 256;
   prep_bias_kernel<R><<<nb, 256, 0, st>>>(p, c->P_rbm, c->K, c->M, c->N, c->d.use_bias,

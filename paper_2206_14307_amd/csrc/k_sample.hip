@@ -83,8 +83,9 @@ __device__ __forceinline__ int select128(uint64_t lo, uint64_t hi, int k) {
 template <typename R>
 __global__ __launch_bounds__(1024) void sample_kernel(
     int N, int G, int K, int M, int n_htiles, const uint8_t* __restrict__ perminv,
-    const R* __restrict__ Tpair, const R* __restrict__ Fpair, R* __restrict__ t, R* __restrict__ w,
-    uint64_t* __restrict__ state, int n_prop, int phase, int64_t p0, const int32_t* nskip_dev,
+    const R* __restrict__ Tpair, const R* __restrict__ Fpair, R* __restrict__ t, R* __restrict__ t2,
+    R* __restrict__ w, uint64_t* __restrict__ state, int n_prop, int phase, int64_t p0,
+    const int32_t* nskip_dev,
     int n_skip_host, uint64_t seed, int8_t* __restrict__ spins_out, int64_t n_per_chain,
     int64_t* __restrict__ acc_out, int8_t* __restrict__ cur_spins) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -102,7 +103,12 @@ __global__ __launch_bounds__(1024) void sample_kernel(
                      ((lo & ~nmask_lo) == 0) && ((hi & ~nmask_hi) == 0);
   const int n_skip = phase == 1 ? (nskip_dev ? *nskip_dev : n_skip_host) : 1;
   const int KM = K * M;
+  // tanh(theta) of the current state (tc) and of the proposed one (tn): the
+  // ratio pass also writes the tanh-addition update of every entry to tn, and
+  // an accepted proposal swaps the two (the acceptance rate is close to 1, so
+  // this reads the cache once per proposal instead of twice)
   R* tc = t + (size_t)c * n_htiles * G * 16;
+  R* tn = t2 + (size_t)c * n_htiles * G * 16;
   R* wc = w + (size_t)c * K * G * 2;
   int64_t acc = 0;
   for (int r = 0; r < n_prop && valid; ++r) {
@@ -122,15 +128,21 @@ __global__ __launch_bounds__(1024) void sample_kernel(
         R pr = 1, pi = 0;
         for (int h8 = k * M; h8 < (k + 1) * M; h8 += 8) {
           const R* tp = tc + ((size_t)(h8 >> 3) * G + g) * 16;
+          R* up = tn + ((size_t)(h8 >> 3) * G + g) * 16;
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             const R tr = tp[2 * e], ti = tp[2 * e + 1];
             const R Tr = Trow[2 * (h8 + e)], Ti = Trow[2 * (h8 + e) + 1];
-            const R a = fmaf_t(tr, Tr, fmaf_t(-ti, Ti, R(-1)));
+            const R a = fmaf_t(tr, Tr, fmaf_t(-ti, Ti, R(-1)));   // a + ib = t T - 1
             const R b = fmaf_t(tr, Ti, ti * Tr);
             const R nr = fmaf_t(pr, a, -(pi * b));
             pi = fmaf_t(pr, b, pi * a);
             pr = nr;
+            // t' = (t - T) / (1 - t T) = (T - t) / (a + ib)
+            const R dr = Tr - tr, di = Ti - ti;
+            const R inv = R(1) / (a * a + b * b);
+            up[2 * e] = (dr * a + di * b) * inv;
+            up[2 * e + 1] = (di * a - dr * b) * inv;
           }
         }
         const R* f = Fpair + (((size_t)k * N + l1) * N + l2) * 2;
@@ -159,22 +171,10 @@ __global__ __launch_bounds__(1024) void sample_kernel(
     const bool accept = u < sr * sr + si * si;
     if (accept) {
       ++acc;
+      R* const sw = tc;                        // the updated cache becomes current
+      tc = tn;
+      tn = sw;
       if (active) {
-        const R* Trow = Tpair + ((size_t)l1 * N + l2) * KM * 2;
-        for (int h8 = 0; h8 < KM; h8 += 8) {
-          R* tp = tc + ((size_t)(h8 >> 3) * G + g) * 16;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const R tr = tp[2 * e], ti = tp[2 * e + 1];
-            const R Tr = Trow[2 * (h8 + e)], Ti = Trow[2 * (h8 + e) + 1];
-            // (t - T) / (1 - t T)
-            const R nr = tr - Tr, ni = ti - Ti;
-            const R dr = R(1) - (tr * Tr - ti * Ti), di = -(tr * Ti + ti * Tr);
-            const R inv = R(1) / (dr * dr + di * di);
-            tp[2 * e] = (nr * dr + ni * di) * inv;
-            tp[2 * e + 1] = (ni * dr - nr * di) * inv;
-          }
-        }
         const double den = sr * sr + si * si;
         for (int k = 0; k < K; ++k) {
           const R wr = wc[2 * (k * G + g)], wi = wc[2 * (k * G + g) + 1];
@@ -460,8 +460,9 @@ inline size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
 size_t sample_workspace_bytes(const nqs_ctx* c, int64_t C) {
   const size_t rs = c->prec == NQS_FP64 ? 8 : 4, n = (size_t)std::max<int64_t>(C, 1);
-  return al(n * c->G * c->KM * 2 * rs) + al(n * c->K * c->G * 2 * rs) + al(n * c->K * c->G * 16) +
-         al(n * 16) + al(n * c->N) + 2 * al(n * 8) + al(64);
+  // two tanh(theta) caches (current and proposed state) for the streaming kernel
+  return 2 * al(n * c->G * c->KM * 2 * rs) + al(n * c->K * c->G * 2 * rs) +
+         al(n * c->K * c->G * 16) + al(n * 16) + al(n * c->N) + 2 * al(n * 8) + al(64);
 }
 
 }  // namespace nqs
@@ -511,6 +512,8 @@ nqs_status nqs_sample(nqs_ctx* c, int64_t n_chains, int64_t n_per_chain, int32_t
   char* p = (char*)ws;
   void* t = p;
   p += al(n * c->G * c->KM * 2 * rs);
+  void* t2 = p;
+  p += al(n * c->G * c->KM * 2 * rs);
   void* w = p;
   p += al(n * c->K * c->G * 2 * rs);
   double* L = (double*)p;
@@ -552,12 +555,14 @@ nqs_status nqs_sample(nqs_ctx* c, int64_t n_chains, int64_t n_per_chain, int32_t
         if (c->prec == NQS_FP64)
           sample_kernel<double><<<(unsigned)n, threads, lds, st>>>(
               c->N, c->G, c->K, c->M, c->n_htiles, c->dev.perminv, (const double*)c->par.Tpair,
-              (const double*)c->par.Fpair, (double*)t, (double*)w, chain_state, cnt, phase, p0,
+              (const double*)c->par.Fpair, (double*)t, (double*)t2, (double*)w, chain_state, cnt,
+              phase, p0,
               ns_dev, ns_host, seed, spins_out, n_per_chain, acc, cur);
         else
           sample_kernel<float><<<(unsigned)n, threads, lds, st>>>(
               c->N, c->G, c->K, c->M, c->n_htiles, c->dev.perminv, (const float*)c->par.Tpair,
-              (const float*)c->par.Fpair, (float*)t, (float*)w, chain_state, cnt, phase, p0,
+              (const float*)c->par.Fpair, (float*)t, (float*)t2, (float*)w, chain_state, cnt,
+              phase, p0,
               ns_dev, ns_host, seed, spins_out, n_per_chain, acc, cur);
         r = hipGetLastError();
       }

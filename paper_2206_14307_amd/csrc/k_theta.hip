@@ -259,7 +259,7 @@ __global__ __launch_bounds__(256) void theta_kernel(
 #pragma unroll
     for (int b = 0; b < CB; ++b) axr[b] = axi[b] = R(0);
     const R* ak = avec + (size_t)k * N * 2;
-    if constexpr (PREC != NQS_BF16X2) {
+    if constexpr (!bf16_mfma(PREC)) {
 #pragma unroll
       for (int kk = 0; kk < NK; ++kk) {
         const R ar = ak[2 * (4 * kk + q)], ai = ak[2 * (4 * kk + q) + 1];
@@ -386,17 +386,18 @@ hipError_t theta_for(const nqs_ctx* c, const int8_t* spins, int64_t S, double* L
   using R = typename T::R;
   // column blocks per wave: 4 for FP32 / FP64 at N <= 36, otherwise 2 (fewer
   // live registers where the fragments or the MFMA chains are longer)
-  constexpr int CB = (N <= 36 && PREC != NQS_BF16X2) ? 4 : 2;
+  constexpr int CB = (N <= 36 && !bf16_mfma(PREC)) ? 4 : 2;
+  const void* wf = PREC == kPrecF32X3 ? c->par.wfrag3 : c->par.wfrag;
   const int64_t total_cb = S * (c->G / 16);
   const int64_t waves = (total_cb + CB - 1) / CB;
   const int64_t blocks = (waves + 3) / 4;
   if (t_out)
     theta_kernel<N, PREC, CB, true><<<(unsigned)blocks, 256, 0, st>>>(
-        spins, S, c->dev.perm, c->G, (const typename T::AFrag*)c->par.wfrag,
+        spins, S, c->dev.perm, c->G, (const typename T::AFrag*)wf,
         (const R*)c->par.bias, (const R*)c->par.avec, c->K, c->M, c->n_htiles, Lout, (R*)t_out);
   else
     theta_kernel<N, PREC, CB, false><<<(unsigned)blocks, 256, 0, st>>>(
-        spins, S, c->dev.perm, c->G, (const typename T::AFrag*)c->par.wfrag,
+        spins, S, c->dev.perm, c->G, (const typename T::AFrag*)wf,
         (const R*)c->par.bias, (const R*)c->par.avec, c->K, c->M, c->n_htiles, Lout, nullptr);
   return hipGetLastError();
 }
@@ -406,7 +407,12 @@ hipError_t theta_prec(const nqs_ctx* c, const int8_t* spins, int64_t S, double* 
                       hipStream_t st) {
   switch (c->prec) {
     case NQS_FP64: return theta_for<N, NQS_FP64>(c, spins, S, Lout, t_out, st);
-    case NQS_FP32: return theta_for<N, NQS_FP32>(c, spins, S, Lout, t_out, st);
+    // FP32 models: theta from the three-term BF16 split of W (FP32 numerics)
+    // up to 6x6; beyond, its longer fragment chains cost occupancy (the
+    // pipelined tile loop holds two tiles' fragments)
+    case NQS_FP32:
+      if constexpr (N <= 36) return theta_for<N, kPrecF32X3>(c, spins, S, Lout, t_out, st);
+      else return theta_for<N, NQS_FP32>(c, spins, S, Lout, t_out, st);
     default: return theta_for<N, NQS_BF16X2>(c, spins, S, Lout, t_out, st);
   }
 }

@@ -28,8 +28,26 @@ template <> struct ThetaTraits<NQS_BF16X2> {
   using AFrag = bf16x8;
 };
 
+// Internal precision tag: FP32 theta on BF16 MFMA from an exact three-term
+// BF16 split of W, K axis [W_hi | W_mid | W_lo | 0] against [x | x | x | 0].
+// x = +-1/2 is exact in BF16 and W_hi + W_mid + W_lo == W (split3 of the
+// FP32 W), so the products are the exact FP32 products and only the FP32
+// accumulation rounds -- the numerics of the FP32 MFMA form.
+constexpr int kPrecF32X3 = 16;
+template <> struct ThetaTraits<kPrecF32X3> {
+  using R = float;
+  using Acc = f32x4;
+  using BFrag = bf16x8;
+  using AFrag = bf16x8;
+};
+// theta runs on 16x16x32 BF16 MFMA; copies of x along the K axis
+__host__ __device__ constexpr bool bf16_mfma(int prec) {
+  return prec == NQS_BF16X2 || prec == kPrecF32X3;
+}
+__host__ __device__ constexpr int x_copies(int prec) { return prec == kPrecF32X3 ? 3 : 2; }
+
 template <int N, int PREC> constexpr int nk_of() {
-  return PREC == NQS_BF16X2 ? (2 * N + 31) / 32 : N / 4;
+  return bf16_mfma(PREC) ? (x_copies(PREC) * N + 31) / 32 : N / 4;
 }
 
 __device__ __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
@@ -115,14 +133,15 @@ __device__ __forceinline__ uint32_t x_bits(const SpinBits& m, int p) {
 }
 
 // Build the B-operand fragments of one 16-image column block: lane (q, c)
-// holds sites 4 kk + q of image c (FP32 / FP64), or for split BF16 the K
-// positions 32 kk + 8 q + e of [x | x | 0].
+// holds sites 4 kk + q of image c (FP32 / FP64), or for the BF16 forms the K
+// positions 32 kk + 8 q + e of [x | x | 0] (split BF16) or [x | x | x | 0].
 template <int N, int PREC>
 __device__ __forceinline__ SpinBits load_bfrag(const int8_t* srow, const uint8_t* prow, int q,
                                                typename ThetaTraits<PREC>::BFrag* bx) {
   constexpr int NK = nk_of<N, PREC>();
+  constexpr int XC = x_copies(PREC);
   const SpinBits m = spin_bits<N>(srow);
-  if constexpr (PREC == NQS_BF16X2) {
+  if constexpr (bf16_mfma(PREC)) {
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
       uint32_t w[4];
@@ -132,7 +151,7 @@ __device__ __forceinline__ SpinBits load_bfrag(const int8_t* srow, const uint8_t
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int kap = 32 * kk + 8 * q + 2 * e2 + h;
-          half[h] = kap < 2 * N ? x_bits<N>(m, prow[kap < N ? kap : kap - N]) : 0u;
+          half[h] = kap < XC * N ? x_bits<N>(m, prow[kap % N]) : 0u;
         }
         w[e2] = (half[0] >> 16) | (half[1] & 0xffff0000u);   // two BF16, low element first
       }
@@ -152,7 +171,7 @@ template <int N, int PREC>
 __device__ __forceinline__ void load_bfrag_gather(const int8_t* srow, const uint8_t* prow, int q,
                                                   typename ThetaTraits<PREC>::BFrag* bx) {
   constexpr int NK = nk_of<N, PREC>();
-  if constexpr (PREC == NQS_BF16X2) {
+  if constexpr (bf16_mfma(PREC)) {
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
       bf16x8 v;
@@ -160,7 +179,7 @@ __device__ __forceinline__ void load_bfrag_gather(const int8_t* srow, const uint
       for (int e = 0; e < 8; ++e) {
         const int kap = 32 * kk + 8 * q + e;
         float x = 0.f;
-        if (kap < 2 * N) x = 0.5f * (float)srow[prow[kap < N ? kap : kap - N]];
+        if (kap < x_copies(PREC) * N) x = 0.5f * (float)srow[prow[kap % N]];
         v[e] = (__bf16)x;
       }
       bx[kk] = v;

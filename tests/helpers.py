@@ -108,6 +108,20 @@ def max_scaled_eloc_err(got, ref, scale):
     return float((np.abs(got - ref) / np.maximum(1.0, np.asarray(scale))).max())
 
 
+def logpsi_error_scale(model, params, spins):
+    """kappa_psi = sum_{k,g} |psi_s^(k)(g sigma)| / |psi(sigma)| per
+    configuration: the size of log psi's terms relative to the sum (1 when
+    the images add up without cancelling)."""
+    import oracle
+    w, _, _ = oracle.image_weights(model, params, spins)
+    return np.abs(w).sum(axis=(1, 2))
+
+
+def max_scaled_logpsi_err(a, b, kappa):
+    """max |wrapped (a - b)| / kappa (log psi to the size of its terms)."""
+    return float((np.abs(wrap_diff(np.asarray(a), np.asarray(b))) / np.asarray(kappa)).max())
+
+
 def grad_error_scale(model, params, spins):
     """||sum_{k,g} |w_kg| |t_kgh| |x_gj| ||_2 per configuration, over the
     same [W | a | b] layout as the oracle's log-derivatives."""
