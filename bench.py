@@ -49,7 +49,7 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6          # MI355X published FP64 vector (and MFMA) peak
 FLOPS_PER_FACTOR = 10            # one exchange factor P <- P (1 + s t T), counted as 10 flops
-CPU_SHARE = 16                   # worker processes the GPU machine grants one GPU's job
+CPU_SHARE = 16                   # host cores per GPU on the MI355X hosts measured (one GPU's share)
 
 
 def log(msg):
@@ -705,7 +705,7 @@ def main():
         print(json.dumps(write_counters(*args.write_counters), indent=1))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the hot path is measured at "
+        print(json.dumps({"error": "this benchmark runs on one GPU: the hot path is measured at "
                                    "--gpus 1 only (the multi-GPU sharding is a design, "
                                    "not an implementation)"}))
         sys.exit(2)
