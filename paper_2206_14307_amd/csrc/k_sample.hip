@@ -90,7 +90,9 @@ __global__ __launch_bounds__(1024) void sample_kernel(
     int64_t* __restrict__ acc_out, int8_t* __restrict__ cur_spins) {
   extern __shared__ __align__(16) unsigned char smem[];
   R* Rg = reinterpret_cast<R*>(smem);                                  // [G][K] complex
-  double* red = reinterpret_cast<double*>(smem + (size_t)G * K * 2 * sizeof(R));  // [2][16]
+  // per-wave ratio sums [2][32], double-buffered by proposal parity (see the
+  // register kernel): one barrier per proposal
+  double* red = reinterpret_cast<double*>(smem + (size_t)G * K * 2 * sizeof(R));
   const int64_t c = blockIdx.x;
   const int g = threadIdx.x, lane = g & 63, wv = g >> 6, nw = (blockDim.x + 63) >> 6;
   const bool active = g < G;
@@ -156,17 +158,17 @@ __global__ __launch_bounds__(1024) void sample_kernel(
     }
     cr = wave_sum(cr);
     ci = wave_sum(ci);
+    double* rb = red + 32 * (r & 1);
     if (lane == 0) {
-      red[wv] = cr;
-      red[16 + wv] = ci;
+      rb[wv] = cr;
+      rb[16 + wv] = ci;
     }
     __syncthreads();
     double sr = 0.0, si = 0.0;
     for (int q = 0; q < nw; ++q) {
-      sr += red[q];
-      si += red[16 + q];
+      sr += rb[q];
+      si += rb[16 + q];
     }
-    __syncthreads();
     const double u = (double)(rnd[2] >> 11) * (1.0 / 9007199254740992.0);
     const bool accept = u < sr * sr + si * si;
     if (accept) {
@@ -226,7 +228,10 @@ __global__ __launch_bounds__(640) void sample_reg_kernel(
     int n_skip_host, uint64_t seed, int8_t* __restrict__ spins_out, int64_t n_per_chain,
     int64_t* __restrict__ acc_out, int8_t* __restrict__ cur_spins) {
   constexpr int MH = M / SPLIT;                  // hidden units per lane
-  __shared__ double red[32];
+  // per-wave ratio sums, double-buffered by proposal parity: proposal r + 2
+  // writes a buffer only after every wave passed proposal r + 1's barrier,
+  // i.e. after every wave read proposal r's sums
+  __shared__ double red[2][32];
   extern __shared__ uint8_t pinv[];              // [G][N] inverse permutations (G N bytes)
   __shared__ uint64_t rbuf[64][3];               // random words of the next 64 proposals
   const int64_t c = blockIdx.x;
@@ -317,17 +322,17 @@ __global__ __launch_bounds__(640) void sample_reg_kernel(
     }
     cr = wave_sum(cr);
     ci = wave_sum(ci);
+    double* rb = red[r & 1];
     if (lane == 0) {
-      red[wv] = cr;
-      red[16 + wv] = ci;
+      rb[wv] = cr;
+      rb[16 + wv] = ci;
     }
     __syncthreads();
     double sr = 0.0, si = 0.0;
     for (int q = 0; q < nw; ++q) {
-      sr += red[q];
-      si += red[16 + q];
+      sr += rb[q];
+      si += rb[16 + q];
     }
-    __syncthreads();
     const double u = (double)(rnd[2] >> 11) * (1.0 / 9007199254740992.0);
     const double den = sr * sr + si * si;
     if (u < den) {
@@ -536,7 +541,7 @@ nqs_status nqs_sample(nqs_ctx* c, int64_t n_chains, int64_t n_per_chain, int32_t
     e = hipGetLastError();
   }
   const int threads = std::max(64, (c->G + 63) / 64 * 64);
-  const size_t lds = (size_t)c->G * c->K * 2 * rs + 32 * sizeof(double);
+  const size_t lds = (size_t)c->G * c->K * 2 * rs + 64 * sizeof(double);
   auto refresh = [&]() -> hipError_t {
     hipError_t r = launch_theta(c, cur, n_chains, L, t, st);
     if (r == hipSuccess) r = launch_lse(c, L, n_chains, lp, w, st);
