@@ -376,6 +376,279 @@ __global__ __launch_bounds__(640) void sample_reg_kernel(
   }
 }
 
+// DPP lane exchanges within a 16-lane row (every lane active): quad_perm
+// (1,0,3,2) pairs lane ^ 1, quad_perm (2,3,0,1) lane ^ 2, row_half_mirror the
+// other quad of an 8-lane half row, row_mirror the other half of the row.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, b.x, CTRL, 0xF, 0xF, false);
+  r.y = __builtin_amdgcn_update_dpp(0, b.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, r);
+}
+// Sum over the 64 lanes of a wave (all active), the same value in every lane:
+// butterfly within each row, then the four row sums read as scalars.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<kDppXor1>(v);
+  v += dpp_f64<kDppXor2>(v);
+  v += dpp_f64<kDppHalfMirror>(v);
+  v += dpp_f64<kDppMirror>(v);
+  const int2 b = __builtin_bit_cast(int2, v);
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int2 q;
+    q.x = __builtin_amdgcn_readlane(b.x, 16 * r);
+    q.y = __builtin_amdgcn_readlane(b.y, 16 * r);
+    s += __builtin_bit_cast(double, q);
+  }
+  return s;
+}
+// Complex product over groups of LPE consecutive lanes (LPE in {1, 2, 4, 8,
+// 16}); every lane of a group ends with the group's product (up to the last
+// bit of the imaginary part, whose rounding depends on the operand order).
+template <int LPE>
+__device__ __forceinline__ void group_cmul(float& pr, float& pi) {
+  auto step = [&](float orr, float oi) {
+    const float nr = fmaf_t(pr, orr, -(pi * oi));
+    pi = fmaf_t(pr, oi, pi * orr);
+    pr = nr;
+  };
+  if constexpr (LPE >= 2) step(dpp_f32<kDppXor1>(pr), dpp_f32<kDppXor1>(pi));
+  if constexpr (LPE >= 4) step(dpp_f32<kDppXor2>(pr), dpp_f32<kDppXor2>(pi));
+  if constexpr (LPE >= 8) step(dpp_f32<kDppHalfMirror>(pr), dpp_f32<kDppHalfMirror>(pi));
+  if constexpr (LPE >= 16) step(dpp_f32<kDppMirror>(pr), dpp_f32<kDppMirror>(pi));
+}
+
+// tanh addition t' = (t - T) / (1 - t T), in place
+__device__ __forceinline__ void tanh_add(float& tr, float& ti, float Tr, float Ti) {
+  const float nr = tr - Tr, ni = ti - Ti;
+  const float dr = fmaf_t(ti, Ti, fmaf_t(-tr, Tr, 1.f));
+  const float di = fmaf_t(tr, Ti, ti * Tr);             // 1 - t T = dr - i di
+  const float inv = rcp_fast(fmaf_t(dr, dr, di * di));
+  tr = fmaf_t(nr, dr, -(ni * di)) * inv;
+  ti = fmaf_t(ni, dr, nr * di) * inv;
+}
+// p *= t T - 1
+__device__ __forceinline__ void mul_factor(float& pr, float& pi, float tr, float ti, float Tr,
+                                           float Ti) {
+  const float a = fmaf_t(tr, Tr, fmaf_t(-ti, Ti, -1.f));
+  const float b = fmaf_t(tr, Ti, ti * Tr);
+  const float nr = fmaf_t(pr, a, -(pi * b));
+  pi = fmaf_t(pr, b, pi * a);
+  pr = nr;
+}
+
+// Register-resident variant for one FP32 RBM whose G = 32 IPG images and M =
+// 8 UPL hidden units give every lane of a 256-lane workgroup (one wave per
+// SIMD) IPG x UPL units: lane (group gi = l / 8, k = l % 8) holds units
+// h = k + 8 s (s < UPL) of images g = 32 m + gi (m < IPG).  The eight lanes of
+// a group thus read each site-pair row in contiguous 64-byte pieces (a row
+// read per lane would make every lane of a load its own cache access, which
+// bounds the L1 address path), and combine their partial products over the
+// group.  Lane k owns images m = k (mod 8): their weights u and ratios.  At
+// most 256 VGPRs a lane leave room for two chains per compute unit.
+template <int M, int IPG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void
+sample_reg8_kernel(int N, int G, int n_htiles, const uint8_t* __restrict__ perminv,
+                   const float* __restrict__ Tpair, const float* __restrict__ Fpair,
+                   const float* __restrict__ t, const float* __restrict__ w,
+                   uint64_t* __restrict__ state, int n_prop, int phase, int64_t p0,
+                   int n_skip_host, uint64_t seed, int8_t* __restrict__ spins_out,
+                   int64_t n_per_chain, int64_t* __restrict__ acc_out,
+                   int8_t* __restrict__ cur_spins) {
+  static_assert(M % 8 == 0, "eight lanes per image");
+  constexpr int UPL = M / 8, NSLOT = (IPG + 7) / 8;
+  // per-wave ratio sums (re 0..3, im 4..7), double-buffered by proposal parity
+  __shared__ double red[2][8];
+  extern __shared__ uint8_t pinv[];              // [G][N] inverse permutations
+  __shared__ uint64_t rbuf[64][3];               // random words of the next 64 proposals
+  const int64_t c = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int gi = tid >> 3, k = tid & 7;
+  uint64_t lo = state[4 * c], hi = state[4 * c + 1], ctr = state[4 * c + 2];
+  const uint64_t id = state[4 * c + 3];
+  const uint64_t nmask_lo = N >= 64 ? ~0ull : ((1ull << N) - 1ull);
+  const uint64_t nmask_hi = N > 64 ? ((1ull << (N - 64)) - 1ull) : 0ull;
+  const int half = N / 2;
+  const bool valid = (__popcll(lo & nmask_lo) + __popcll(hi & nmask_hi) == half) &&
+                     ((lo & ~nmask_lo) == 0) && ((hi & ~nmask_hi) == 0);
+  const int n_skip = phase == 1 ? n_skip_host : 1;
+  float tr[IPG][UPL], ti[IPG][UPL];
+  float wr[NSLOT], wi[NSLOT];
+  {
+    const float* tc = t + (size_t)c * n_htiles * G * 16;
+#pragma unroll
+    for (int m = 0; m < IPG; ++m)
+#pragma unroll
+      for (int s = 0; s < UPL; ++s) {
+        const size_t o = ((size_t)s * G + 32 * m + gi) * 16 + 2 * k;
+        tr[m][s] = tc[o];
+        ti[m][s] = tc[o + 1];
+      }
+    const float* wc = w + (size_t)c * G * 2;
+#pragma unroll
+    for (int q = 0; q < NSLOT; ++q) {
+      const int m = k + 8 * q < IPG ? k + 8 * q : k;   // lanes without a second image
+      wr[q] = wc[2 * (32 * m + gi)];
+      wi[q] = wc[2 * (32 * m + gi) + 1];
+    }
+  }
+  for (int e = tid; e < G * N; e += 256) pinv[e] = perminv[e];
+  __syncthreads();
+  const float2* T2 = reinterpret_cast<const float2*>(Tpair) + k;
+  int64_t acc = 0;
+  for (int r = 0; r < n_prop && valid; ++r) {
+    if ((r & 63) == 0) {
+      __syncthreads();
+      if (tid < 64) {
+        uint64_t rr[4];
+        philox4x64_10(ctr + (uint64_t)tid, 0, 0, 0, seed, id, rr);
+        rbuf[tid][0] = rr[0];
+        rbuf[tid][1] = rr[1];
+        rbuf[tid][2] = rr[2];
+      }
+      __syncthreads();
+    }
+    const uint64_t r0 = rbuf[r & 63][0], r1 = rbuf[r & 63][1], r2 = rbuf[r & 63][2];
+    const int kup = (int)(((r0 >> 11) * (uint64_t)half) >> 53);
+    const int kdn = (int)(((r1 >> 11) * (uint64_t)half) >> 53);
+    const int i = select128(lo, hi, kup);
+    const int j = select128(~lo & nmask_lo, ~hi & nmask_hi, kdn);
+    // site-pair row of every image (row index p N + q, p/q the sites of i/j)
+    int row[IPG];
+#pragma unroll
+    for (int m = 0; m < IPG; ++m)
+      row[m] = (int)pinv[(32 * m + gi) * N + i] * N + pinv[(32 * m + gi) * N + j];
+    // ratio pass: per image, the lane's partial product of (t T - 1), then
+    // the group's product; rows read one image ahead
+    // (the prefactor F is read with its row: a load issued after the next
+    // image's rows would make its wait cover them too)
+    const float2* F2 = reinterpret_cast<const float2*>(Fpair);
+    float Rr[NSLOT], Ri[NSLOT];
+    float2 buf[2][UPL], fb[2];
+#pragma unroll
+    for (int s = 0; s < UPL; ++s) buf[0][s] = T2[(size_t)row[0] * M + 8 * s];
+    fb[0] = F2[row[0]];
+#pragma unroll
+    for (int m = 0; m < IPG; ++m) {
+      if (m + 1 < IPG) {
+#pragma unroll
+        for (int s = 0; s < UPL; ++s) buf[(m + 1) & 1][s] = T2[(size_t)row[m + 1] * M + 8 * s];
+        fb[(m + 1) & 1] = F2[row[m + 1]];
+      }
+      float pr = 1.f, pi = 0.f;
+#pragma unroll
+      for (int s = 0; s < UPL; ++s)
+        mul_factor(pr, pi, tr[m][s], ti[m][s], buf[m & 1][s].x, buf[m & 1][s].y);
+      group_cmul<8>(pr, pi);
+      const float2 f = fb[m & 1];
+      const float rr = f.x * pr - f.y * pi, ri = f.x * pi + f.y * pr;
+      if (k == (m & 7)) {
+        Rr[m >> 3] = rr;
+        Ri[m >> 3] = ri;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    double cr = 0.0, ci = 0.0;
+#pragma unroll
+    for (int q = 0; q < NSLOT; ++q)
+      if (k + 8 * q < IPG) {
+        cr += (double)(wr[q] * Rr[q] - wi[q] * Ri[q]);
+        ci += (double)(wr[q] * Ri[q] + wi[q] * Rr[q]);
+      }
+    cr = wave_sum_dpp(cr);
+    ci = wave_sum_dpp(ci);
+    double* rb = red[r & 1];
+    if (lane == 0) {
+      rb[wv] = cr;
+      rb[4 + wv] = ci;
+    }
+    __syncthreads();
+    const double sr = (rb[0] + rb[1]) + (rb[2] + rb[3]);
+    const double si = (rb[4] + rb[5]) + (rb[6] + rb[7]);
+    const double u = (double)(r2 >> 11) * (1.0 / 9007199254740992.0);
+    const double den = sr * sr + si * si;
+    // every lane holds the same sums: a wave-uniform decision
+    if (__builtin_amdgcn_readfirstlane((int)(u < den))) {
+      ++acc;
+      const uint64_t mi = 1ull << (i & 63), mj = 1ull << (j & 63);
+      lo ^= (i < 64 ? mi : 0ull) ^ (j < 64 ? mj : 0ull);
+      hi ^= (i < 64 ? 0ull : mi) ^ (j < 64 ? 0ull : mj);
+      // u' = u R / ratio
+      const double id2 = 1.0 / den;
+#pragma unroll
+      for (int q = 0; q < NSLOT; ++q) {
+        const double ar = (double)(wr[q] * Rr[q] - wi[q] * Ri[q]);
+        const double ai = (double)(wr[q] * Ri[q] + wi[q] * Rr[q]);
+        wr[q] = (float)((ar * sr + ai * si) * id2);
+        wi[q] = (float)((ai * sr - ar * si) * id2);
+      }
+      // t' = (t - T) / (1 - t T).  The rows are read again, one image ahead;
+      // an opaque zero offset keeps the compiler from hoisting these loads
+      // above the acceptance test (registers for all of them at once)
+      int z = 0;
+      asm volatile("" : "+v"(z));
+#pragma unroll
+      for (int s = 0; s < UPL; ++s) buf[0][s] = T2[(size_t)row[0] * M + 8 * s + z];
+#pragma unroll
+      for (int m = 0; m < IPG; ++m) {
+        if (m + 1 < IPG) {
+#pragma unroll
+          for (int s = 0; s < UPL; ++s)
+            buf[(m + 1) & 1][s] = T2[(size_t)row[m + 1] * M + 8 * s + z];
+        }
+#pragma unroll
+        for (int s = 0; s < UPL; ++s)
+          tanh_add(tr[m][s], ti[m][s], buf[m & 1][s].x, buf[m & 1][s].y);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    ++ctr;
+    if (phase == 1) {
+      const int64_t idx = p0 + r + 1;
+      if (idx % n_skip == 0) {
+        const int64_t m = idx / n_skip - 1;
+        if (m < n_per_chain && tid < N) {
+          const uint64_t bit = tid < 64 ? (lo >> tid) & 1ull : (hi >> (tid - 64)) & 1ull;
+          spins_out[((size_t)c * n_per_chain + m) * N + tid] = bit ? 1 : -1;
+        }
+      }
+    }
+  }
+  if (tid == 0) {
+    state[4 * c] = lo;
+    state[4 * c + 1] = hi;
+    state[4 * c + 2] = ctr;
+    acc_out[c] += valid ? acc : -((int64_t)1 << 40);
+  }
+  if (tid < N) {
+    const uint64_t bit = tid < 64 ? (lo >> tid) & 1ull : (hi >> (tid - 64)) & 1ull;
+    cur_spins[(size_t)c * N + tid] = bit ? 1 : -1;
+  }
+}
+
+template <int M, int IPG>
+hipError_t launch_reg8(const nqs_ctx* c, int64_t n, const void* t, const void* w,
+                       uint64_t* state, int cnt, int phase, int64_t p0, int ns, uint64_t seed,
+                       int8_t* spins_out, int64_t n_per_chain, int64_t* acc, int8_t* cur,
+                       hipStream_t st) {
+  if (c->G != 32 * IPG || c->M != M || c->N > 128) return hipErrorNotSupported;
+  sample_reg8_kernel<M, IPG><<<(unsigned)n, 256, (size_t)c->G * c->N, st>>>(
+      c->N, c->G, c->n_htiles, c->dev.perminv, (const float*)c->par.Tpair,
+      (const float*)c->par.Fpair, (const float*)t, (const float*)w, state, cnt, phase, p0, ns,
+      seed, spins_out, n_per_chain, acc, cur);
+  return hipGetLastError();
+}
+
 template <typename R, int M, int SPLIT>
 hipError_t launch_reg(const nqs_ctx* c, int64_t n, const void* t, const void* w,
                       uint64_t* state, int cnt, int phase, int64_t p0, int ns, uint64_t seed,
@@ -396,6 +669,10 @@ hipError_t try_reg(const nqs_ctx* c, int64_t n, const void* t, const void* w, ui
                    int64_t n_per_chain, int64_t* acc, int8_t* cur, hipStream_t st) {
   // FP32 only: the FP64 path (small lattices) stays on the cache-streaming kernel
   if (c->K != 1 || c->G > 512 || c->prec == NQS_FP64) return hipErrorNotSupported;
+  // 6x6 (G = 288) with M = 72: eight lanes per image, 256 lanes per chain
+  if (c->G == 288 && c->M == 72)
+    return launch_reg8<72, 9>(c, n, t, w, state, cnt, phase, p0, ns, seed, spins_out,
+                              n_per_chain, acc, cur, st);
 #define NQS_REG_CASE(MM, SP)                                                                 \
   if (c->M == MM)                                                                            \
     return launch_reg<float, MM, SP>(c, n, t, w, state, cnt, phase, p0, ns, seed, spins_out, \
