@@ -381,17 +381,19 @@ __global__ __launch_bounds__(640) void sample_reg_kernel(
 // other quad of an 8-lane half row, row_mirror the other half of the row.
 constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
 
+// (bound_ctrl set: no lane reads out of its row in these patterns, and no
+// old value has to be copied into the destination first)
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
   return __builtin_bit_cast(
-      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
   const int2 b = __builtin_bit_cast(int2, v);
   int2 r;
-  r.x = __builtin_amdgcn_update_dpp(0, b.x, CTRL, 0xF, 0xF, false);
-  r.y = __builtin_amdgcn_update_dpp(0, b.y, CTRL, 0xF, 0xF, false);
+  r.x = __builtin_amdgcn_mov_dpp(b.x, CTRL, 0xF, 0xF, true);
+  r.y = __builtin_amdgcn_mov_dpp(b.y, CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, r);
 }
 // Sum over the 64 lanes of a wave (all active), the same value in every lane:
@@ -448,14 +450,17 @@ __device__ __forceinline__ void mul_factor(float& pr, float& pi, float tr, float
 }
 
 // Register-resident variant for one FP32 RBM whose G = 32 IPG images and M =
-// 8 UPL hidden units give every lane of a 256-lane workgroup (one wave per
-// SIMD) IPG x UPL units: lane (group gi = l / 8, k = l % 8) holds units
-// h = k + 8 s (s < UPL) of images g = 32 m + gi (m < IPG).  The eight lanes of
-// a group thus read each site-pair row in contiguous 64-byte pieces (a row
-// read per lane would make every lane of a load its own cache access, which
-// bounds the L1 address path), and combine their partial products over the
-// group.  Lane k owns images m = k (mod 8): their weights u and ratios.  At
-// most 256 VGPRs a lane leave room for two chains per compute unit.
+// 16 P + 8 R (R = 0 or 1) hidden units give every lane of a 256-lane
+// workgroup (one wave per SIMD) IPG x UPL units, UPL = M / 8: lane (group
+// gi = l / 8, k = l % 8) holds units 16 p + 2 k, 16 p + 2 k + 1 (p < P) and,
+// if R = 1, 16 P + k, of images g = 32 m + gi (m < IPG).  The eight lanes of
+// a group thus read each site-pair row in contiguous 128-byte pieces of
+// 16-byte loads (and one 64-byte piece of 8-byte loads): a row read per lane
+// would make every lane of a load its own cache access, and narrower loads
+// cost the L1 address path the same per lane for half the bytes.  The group
+// combines its partial products; lane k owns images m = k (mod 8), their
+// weights u and ratios.  At most 256 VGPRs a lane leave room for two chains
+// per compute unit.
 template <int M, int IPG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void
 sample_reg8_kernel(int N, int G, int n_htiles, const uint8_t* __restrict__ perminv,
@@ -466,7 +471,7 @@ sample_reg8_kernel(int N, int G, int n_htiles, const uint8_t* __restrict__ permi
                    int64_t n_per_chain, int64_t* __restrict__ acc_out,
                    int8_t* __restrict__ cur_spins) {
   static_assert(M % 8 == 0, "eight lanes per image");
-  constexpr int UPL = M / 8, NSLOT = (IPG + 7) / 8;
+  constexpr int P = M / 16, R = (M % 16) / 8, UPL = M / 8, NSLOT = (IPG + 7) / 8;
   // per-wave ratio sums (re 0..3, im 4..7), double-buffered by proposal parity
   __shared__ double red[2][8];
   extern __shared__ uint8_t pinv[];              // [G][N] inverse permutations
@@ -489,10 +494,11 @@ sample_reg8_kernel(int N, int G, int n_htiles, const uint8_t* __restrict__ permi
 #pragma unroll
     for (int m = 0; m < IPG; ++m)
 #pragma unroll
-      for (int s = 0; s < UPL; ++s) {
-        const size_t o = ((size_t)s * G + 32 * m + gi) * 16 + 2 * k;
-        tr[m][s] = tc[o];
-        ti[m][s] = tc[o + 1];
+      for (int u = 0; u < UPL; ++u) {
+        const int h = u < 2 * P ? 16 * (u >> 1) + 2 * k + (u & 1) : 16 * P + k;
+        const size_t o = ((size_t)(h >> 3) * G + 32 * m + gi) * 16 + 2 * (h & 7);
+        tr[m][u] = tc[o];
+        ti[m][u] = tc[o + 1];
       }
     const float* wc = w + (size_t)c * G * 2;
 #pragma unroll
@@ -504,7 +510,21 @@ sample_reg8_kernel(int N, int G, int n_htiles, const uint8_t* __restrict__ permi
   }
   for (int e = tid; e < G * N; e += 256) pinv[e] = perminv[e];
   __syncthreads();
-  const float2* T2 = reinterpret_cast<const float2*>(Tpair) + k;
+  // lane k's pieces of a row: float4 8 p + k (p < P), float2 16 P + k
+  const float4* T4 = reinterpret_cast<const float4*>(Tpair) + k;
+  const float2* T2 = reinterpret_cast<const float2*>(Tpair) + 16 * P + k;
+  // unit u of a loaded row
+  auto unit = [](const float4 (&b4)[P > 0 ? P : 1], const float2& b2, int u, float& Tr,
+                 float& Ti) {
+    if (u < 2 * P) {
+      const float4 v = b4[u >> 1];
+      Tr = (u & 1) ? v.z : v.x;
+      Ti = (u & 1) ? v.w : v.y;
+    } else {
+      Tr = b2.x;
+      Ti = b2.y;
+    }
+  };
   int64_t acc = 0;
   for (int r = 0; r < n_prop && valid; ++r) {
     if ((r & 63) == 0) {
@@ -534,21 +554,32 @@ sample_reg8_kernel(int N, int G, int n_htiles, const uint8_t* __restrict__ permi
     // image's rows would make its wait cover them too)
     const float2* F2 = reinterpret_cast<const float2*>(Fpair);
     float Rr[NSLOT], Ri[NSLOT];
-    float2 buf[2][UPL], fb[2];
+    float4 b4[2][P > 0 ? P : 1];
+    float2 b2[2], fb[2];
+    auto load_row = [&](int q, int rw) {
 #pragma unroll
-    for (int s = 0; s < UPL; ++s) buf[0][s] = T2[(size_t)row[0] * M + 8 * s];
+      for (int p = 0; p < P; ++p) b4[q][p] = T4[(size_t)rw * (M / 2) + 8 * p];
+      if constexpr (R) b2[q] = T2[(size_t)rw * M];
+    };
+    load_row(0, row[0]);
     fb[0] = F2[row[0]];
 #pragma unroll
     for (int m = 0; m < IPG; ++m) {
       if (m + 1 < IPG) {
-#pragma unroll
-        for (int s = 0; s < UPL; ++s) buf[(m + 1) & 1][s] = T2[(size_t)row[m + 1] * M + 8 * s];
+        load_row((m + 1) & 1, row[m + 1]);
         fb[(m + 1) & 1] = F2[row[m + 1]];
       }
-      float pr = 1.f, pi = 0.f;
+      // the first factor starts the product (a product with 1 + 0i is not
+      // folded away under IEEE semantics)
+      float Tr, Ti;
+      unit(b4[m & 1], b2[m & 1], 0, Tr, Ti);
+      float pr = fmaf_t(tr[m][0], Tr, fmaf_t(-ti[m][0], Ti, -1.f));
+      float pi = fmaf_t(tr[m][0], Ti, ti[m][0] * Tr);
 #pragma unroll
-      for (int s = 0; s < UPL; ++s)
-        mul_factor(pr, pi, tr[m][s], ti[m][s], buf[m & 1][s].x, buf[m & 1][s].y);
+      for (int u = 1; u < UPL; ++u) {
+        unit(b4[m & 1], b2[m & 1], u, Tr, Ti);
+        mul_factor(pr, pi, tr[m][u], ti[m][u], Tr, Ti);
+      }
       group_cmul<8>(pr, pi);
       const float2 f = fb[m & 1];
       const float rr = f.x * pr - f.y * pi, ri = f.x * pi + f.y * pr;
@@ -597,18 +628,16 @@ sample_reg8_kernel(int N, int G, int n_htiles, const uint8_t* __restrict__ permi
       // above the acceptance test (registers for all of them at once)
       int z = 0;
       asm volatile("" : "+v"(z));
-#pragma unroll
-      for (int s = 0; s < UPL; ++s) buf[0][s] = T2[(size_t)row[0] * M + 8 * s + z];
+      load_row(0, row[0] + z);
 #pragma unroll
       for (int m = 0; m < IPG; ++m) {
-        if (m + 1 < IPG) {
+        if (m + 1 < IPG) load_row((m + 1) & 1, row[m + 1] + z);
 #pragma unroll
-          for (int s = 0; s < UPL; ++s)
-            buf[(m + 1) & 1][s] = T2[(size_t)row[m + 1] * M + 8 * s + z];
+        for (int u = 0; u < UPL; ++u) {
+          float Tr, Ti;
+          unit(b4[m & 1], b2[m & 1], u, Tr, Ti);
+          tanh_add(tr[m][u], ti[m][u], Tr, Ti);
         }
-#pragma unroll
-        for (int s = 0; s < UPL; ++s)
-          tanh_add(tr[m][s], ti[m][s], buf[m & 1][s].x, buf[m & 1][s].y);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
