@@ -59,6 +59,33 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t
 // from the spins every segment)
 __device__ __forceinline__ float rcp_fast(float v) { return __builtin_amdgcn_rcpf(v); }
 
+// reciprocal of the squared modulus in the cache update: hardware rcp in
+// FP32 (the cache is rebuilt from the spins every segment), a division in
+// FP64
+__device__ __forceinline__ float recip_t(float v) { return rcp_fast(v); }
+__device__ __forceinline__ double recip_t(double v) { return 1.0 / v; }
+
+// one cache or row tile of 8 complex values, moved in 16-byte pieces (the
+// tiles are 64-byte aligned)
+template <typename R>
+__device__ __forceinline__ void load_tile(R (&d)[16], const R* p) {
+  constexpr int NV = (int)(16 * sizeof(R) / sizeof(uint4));
+  const uint4* q = reinterpret_cast<const uint4*>(p);
+  uint4 v[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = q[i];
+  __builtin_memcpy(d, v, sizeof(v));
+}
+template <typename R>
+__device__ __forceinline__ void store_tile(R* p, const R (&d)[16]) {
+  constexpr int NV = (int)(16 * sizeof(R) / sizeof(uint4));
+  uint4 v[NV];
+  __builtin_memcpy(v, d, sizeof(v));
+  uint4* q = reinterpret_cast<uint4*>(p);
+#pragma unroll
+  for (int i = 0; i < NV; ++i) q[i] = v[i];
+}
+
 // position of the k-th (0-based) set bit of a 64-bit word (k < popcount)
 __device__ __forceinline__ int select64(uint64_t x, int k) {
   int pos = 0;
@@ -128,13 +155,19 @@ __global__ __launch_bounds__(1024) void sample_kernel(
       const R* Trow = Tpair + ((size_t)l1 * N + l2) * KM * 2;
       for (int k = 0; k < K; ++k) {
         R pr = 1, pi = 0;
-        for (int h8 = k * M; h8 < (k + 1) * M; h8 += 8) {
-          const R* tp = tc + ((size_t)(h8 >> 3) * G + g) * 16;
-          R* up = tn + ((size_t)(h8 >> 3) * G + g) * 16;
+        // tiles of 8 units: this image's 16 cache values (one contiguous
+        // piece of the [tile][G][16] layout) and 16 row values, each tile's
+        // loads issued one tile ahead of its use, its updates stored whole
+        const int nt = M / 8;
+        const R* tp = tc + ((size_t)(k * nt) * G + g) * 16;
+        R* up = tn + ((size_t)(k * nt) * G + g) * 16;
+        const R* Tq = Trow + (size_t)2 * k * M;
+        // the 8 factors of a tile into the product, the updated tile stored
+        auto tile = [&](R (&tt)[16], const R (&TT)[16], R* dst) {
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
-            const R tr = tp[2 * e], ti = tp[2 * e + 1];
-            const R Tr = Trow[2 * (h8 + e)], Ti = Trow[2 * (h8 + e) + 1];
+            const R tr = tt[2 * e], ti = tt[2 * e + 1];
+            const R Tr = TT[2 * e], Ti = TT[2 * e + 1];
             const R a = fmaf_t(tr, Tr, fmaf_t(-ti, Ti, R(-1)));   // a + ib = t T - 1
             const R b = fmaf_t(tr, Ti, ti * Tr);
             const R nr = fmaf_t(pr, a, -(pi * b));
@@ -142,10 +175,40 @@ __global__ __launch_bounds__(1024) void sample_kernel(
             pr = nr;
             // t' = (t - T) / (1 - t T) = (T - t) / (a + ib)
             const R dr = Tr - tr, di = Ti - ti;
-            const R inv = R(1) / (a * a + b * b);
-            up[2 * e] = (dr * a + di * b) * inv;
-            up[2 * e + 1] = (di * a - dr * b) * inv;
+            const R inv = recip_t(fmaf_t(a, a, b * b));
+            tt[2 * e] = (dr * a + di * b) * inv;
+            tt[2 * e + 1] = (di * a - dr * b) * inv;
           }
+          store_tile(dst, tt);
+        };
+        // FP32: two register buffers, the next tile always in flight (FP64,
+        // for small lattices only, keeps one: its tiles would not fit twice
+        // in the 128 VGPRs of a 1024-lane workgroup)
+        R t0[16], T0[16], t1[16], T1[16];
+        if constexpr (sizeof(R) == 8) {
+          for (int ht = 0; ht < nt; ++ht) {
+            load_tile(t0, tp + (size_t)ht * G * 16);
+            load_tile(T0, Tq + 16 * ht);
+            tile(t0, T0, up + (size_t)ht * G * 16);
+          }
+        } else {
+          // the loop body is free of conditions (the last prefetch reads the
+          // last tile again): a conditional load is sunk to its use, and a
+          // conditional path makes the wait before a tile cover the next
+          // one's loads too
+          load_tile(t0, tp);
+          load_tile(T0, Tq);
+          int ht = 0;
+          for (; ht + 1 < nt; ht += 2) {
+            load_tile(t1, tp + (size_t)(ht + 1) * G * 16);
+            load_tile(T1, Tq + 16 * (ht + 1));
+            tile(t0, T0, up + (size_t)ht * G * 16);
+            const int h2 = min(ht + 2, nt - 1);
+            load_tile(t0, tp + (size_t)h2 * G * 16);
+            load_tile(T0, Tq + 16 * h2);
+            tile(t1, T1, up + (size_t)(ht + 1) * G * 16);
+          }
+          if (ht < nt) tile(t0, T0, up + (size_t)ht * G * 16);   // odd tile count
         }
         const R* f = Fpair + (((size_t)k * N + l1) * N + l2) * 2;
         const R rr = f[0] * pr - f[1] * pi, ri = f[0] * pi + f[1] * pr;
