@@ -301,13 +301,15 @@ def sample_spins(m, w, seed=2002):
     # per proposal and (image, hidden unit): the exchange factor (10 flops) and,
     # when accepted, the tanh addition (t - T)/(1 - t T) (~20 flops)
     fl = props * w.G * w.n_rbm * w.n_hidden * (FLOPS_PER_FACTOR + 20.0 * acc)
-    # one RBM with M in {8, 16, 32, 72} (FP32) keeps tanh(theta) in registers;
-    # otherwise the chain's cache [G][K M] complex FP32 is read every proposal
-    # and written back on acceptance
+    # one RBM with M in {8, 16, 32, 72} (FP32) keeps tanh(theta) in registers
+    # (6x6 M = 72: eight lanes per image); otherwise the chain's cache
+    # [G][K M] complex FP32 is read every proposal and written back
     reg = w.n_rbm == 1 and w.n_hidden in (8, 16, 32, 72) and w.precision != "fp64" and w.G <= 512
+    reg8 = reg and w.G == 288 and w.n_hidden == 72
     leg = {"workload": w.name, "chains": w.n_chains, "per_chain": w.n_per_chain,
            "burn_in": 20 * w.N, "n_skip": nskip, "acceptance": acc, "seconds": t,
-           "kernel": "sample_reg_kernel" if reg else "sample_kernel",
+           "kernel": ("sample_reg8_kernel" if reg8 else "sample_reg_kernel") if reg
+                     else "sample_kernel",
            "sampler_kernel_ms": k_ms, "sampler_launches": k_n,
            "proposals_per_s": props / t,
            "roofline": {"bound": "alu", "achieved": fl / t / 1e12,
@@ -315,11 +317,14 @@ def sample_spins(m, w, seed=2002):
                         "frac": fl / t / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
                         "flops_per_image_hidden_proposal": "10 + 20 x acceptance"}}
     if not reg:
-        nb = props * w.G * w.n_rbm * w.n_hidden * 8.0 * (1.0 + acc)
+        # the cache and the image's site-pair rows (tables far larger than the
+        # L2) read, the cache written back on acceptance
+        nb = props * w.G * w.n_rbm * w.n_hidden * 8.0 * (2.0 + acc)
         leg["roofline"] = {"bound": "hbm", "achieved": nb / t / 1e9, "peak": PEAK_HBM_GBS,
                            "unit": "GB/s", "frac": nb / t / 1e9 / PEAK_HBM_GBS,
-                           "bytes_per_proposal": "G K M x 8 B x (1 + acceptance): the cache "
-                                                 "read, and written back on acceptance",
+                           "bytes_per_proposal": "G K M x 8 B x (2 + acceptance): the cache "
+                                                 "and the site-pair rows read, the cache "
+                                                 "written back on acceptance",
                            "alu_frac": fl / t / 1e12 / PEAK_FP32_VECTOR_TFLOPS}
     return sp, leg
 
