@@ -651,8 +651,10 @@ def leg_sr(m, w, O, el, steps=1):
 # ------------------------------------------------------------------ the step
 
 class Step:
-    """One pass of the hot path on device-resident configurations: nqs_eloc
-    (log psi + E_loc) then nqs_grad (O_k), outputs kept for the error check."""
+    """One pass of the hot path on device-resident configurations: log psi,
+    E_loc and O_k in one nqs_eloc_grad call (for the wide models the gradient
+    takes its image weights from the E_loc pass), outputs kept for the error
+    check; eloc() and grad() are the two separate calls."""
 
     def __init__(self, m, sp):
         import torch
@@ -664,6 +666,8 @@ class Step:
                                 dtype=torch.uint8, device="cuda")
         self.ws_g = torch.empty(max(256, int(m.lib.nqs_workspace_bytes(m._ctx, 3, self.S))),
                                 dtype=torch.uint8, device="cuda")
+        self.ws_eg = torch.empty(max(256, int(m.lib.nqs_workspace_bytes(m._ctx, 10, self.S))),
+                                 dtype=torch.uint8, device="cuda")
 
     def eloc(self):
         from paper_2206_14307_amd.nqs import _ptr, _stream
@@ -678,8 +682,11 @@ class Step:
                                 _ptr(self.ws_g), self.ws_g.numel(), _stream()), "nqs_grad")
 
     def __call__(self):
-        self.eloc()
-        self.grad()
+        from paper_2206_14307_amd.nqs import _ptr, _stream
+        m = self.m
+        m._check(m.lib.nqs_eloc_grad(m._ctx, _ptr(self.sp), self.S, _ptr(self.lp), _ptr(self.el),
+                                     _ptr(self.O), _ptr(self.ws_eg), self.ws_eg.numel(),
+                                     _stream()), "nqs_eloc_grad")
 
     def rows(self, idx):
         import torch
@@ -779,7 +786,8 @@ def main():
         "config": {"workload": args.workload, "lattice": f"{w.L}x{w.L}", "J2": w.J2,
                    "n_rbm": w.n_rbm, "n_hidden": w.n_hidden, "sym_images": w.G,
                    "configs": S, "theta": w.precision,
-                   "step": "nqs_eloc (log psi + E_loc) + nqs_grad (O_k for W, a, b)",
+                   "step": "nqs_eloc_grad: log psi + E_loc + O_k (W, a, b) in one call, the "
+                           "gradient's image weights from the E_loc pass",
                    "params": "N(0,0.01) complex, seed %d" % w.seed,
                    "spins": "exchange Metropolis samples (nqs_sample, %d chains x %d), seed 2002"
                             % (w.n_chains, w.n_per_chain)},

@@ -68,7 +68,7 @@ typedef enum {
 typedef enum {
     NQS_OP_LOGPSI = 0, NQS_OP_ELOC = 1, NQS_OP_MOMENTS = 2,
     NQS_OP_GRAD = 3, NQS_OP_SR = 4, NQS_OP_SAMPLE = 5, NQS_OP_SQ = 6, NQS_OP_VMC = 7,
-    NQS_OP_CG = 8, NQS_OP_MOMENTS2 = 9
+    NQS_OP_CG = 8, NQS_OP_MOMENTS2 = 9, NQS_OP_ELOC_GRAD = 10
 } nqs_op;
 
 typedef struct {
@@ -213,6 +213,18 @@ nqs_status nqs_lanczos_moments_p2(nqs_ctx* ctx, const int8_t* spins, int64_t S, 
  * (float re, im) otherwise.  logpsi_out (complex [S]) optional. */
 nqs_status nqs_grad(nqs_ctx* ctx, const int8_t* spins, int64_t S, void* O_out, double* logpsi_out,
                     void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* log psi, E_loc and O_k of the same configurations in one call: the outputs of
+ * nqs_eloc (logpsi_out optional, eloc_out) and of nqs_grad (O_out), as one
+ * VMC step needs them (Sec. 3.2: Eq. (10) and the O_k below Eq. (12)).  For
+ * models on the wide E_loc and gradient kernels (K*M > 128) the gradient
+ * takes the per-image log amplitudes of psi_s(g sigma) from the E_loc pass
+ * instead of a theta pass of its own; other models run nqs_eloc, then
+ * nqs_grad.  Results agree with the two separate calls to rounding.
+ * Workspace: nqs_workspace_bytes(NQS_OP_ELOC_GRAD, S). */
+nqs_status nqs_eloc_grad(nqs_ctx* ctx, const int8_t* spins, int64_t S, double* logpsi_out,
+                         double* eloc_out, void* O_out, void* ws, size_t ws_bytes,
+                         hipStream_t stream);
 
 /* Stochastic-reconfiguration step of Eq. (12) with ridge lambda (Sec. 3.4),
  * solved in sample space: O_bar = (O - <O>)/sqrt(S), eps = (E_loc - <E>)/sqrt(S),

@@ -64,6 +64,12 @@ bool composed_moments(const nqs_ctx* c, int op) {
          (eloc_fused_supported(c) || eloc_wide_supported(c));
 }
 size_t fused_part_bytes(const nqs_ctx* c) { return (size_t)(c->G / 16) * 6 * 8; }
+// nqs_eloc_grad shares the per-image log amplitudes of the wide E_loc kernel
+// with the wide gradient kernel (no theta pass of its own)
+bool shared_eloc_grad(const nqs_ctx* c) {
+  return !eloc_fused_supported(c) && eloc_wide_supported(c) && grad_wide_supported(c) &&
+         c->K <= kWideLrawK;
+}
 
 size_t chunk_bytes_per_sample(const nqs_ctx* c, int op) {
   const ChunkSizes z = per_sample(c);
@@ -77,6 +83,9 @@ size_t chunk_bytes_per_sample(const nqs_ctx* c, int op) {
     case NQS_OP_MOMENTS2: return z.L + z.w + z.t + z.partial + z.partial2 + c->N + 48;
     // the wide gradient kernel recomputes tanh(theta): no t buffer
     case NQS_OP_GRAD: return z.L + z.w + (grad_wide_supported(c) ? 16 : z.t);
+    // partials, unreduced log amplitudes, weights, two log psi scratch rows
+    case NQS_OP_ELOC_GRAD:
+      return shared_eloc_grad(c) ? fused_part_bytes(c) + 2 * z.L + z.w + 32 : 0;
     default: return 0;
   }
 }
@@ -113,6 +122,7 @@ struct Work {
   double* logpsi = nullptr;
   double* result = nullptr;
   double* lp = nullptr;            // chunk log psi scratch when the caller wants none
+  double* lp2 = nullptr;           // chunk log psi of the weights pass (nqs_eloc_grad)
   double* e3 = nullptr;            // [S] complex (p = 2 moments)
   int8_t* nb_spins = nullptr;      // [chunk][N] neighbour configurations
   double* nb_lp = nullptr;         // [chunk] complex log psi of the neighbours
@@ -153,8 +163,23 @@ Work plan(const nqs_ctx* c, int op, int64_t S, void* ws) {
     wk.bytes = cv.off;
     return wk;
   }
+  if (op == NQS_OP_ELOC_GRAD && !shared_eloc_grad(c)) {
+    // nqs_eloc, then nqs_grad, in the same workspace
+    wk.bytes = std::max(plan(c, NQS_OP_ELOC, S, nullptr).bytes,
+                        plan(c, NQS_OP_GRAD, S, nullptr).bytes);
+    return wk;
+  }
   const int64_t ch = chunk_of(c, op, S);
   wk.chunk = ch;
+  if (op == NQS_OP_ELOC_GRAD) {
+    wk.partial = (double*)cv.take(fused_part_bytes(c) * ch);
+    wk.L = (double*)cv.take(2 * z.L * ch);
+    wk.w = cv.take(z.w * ch);
+    wk.lp = (double*)cv.take((size_t)16 * ch);
+    wk.lp2 = (double*)cv.take((size_t)16 * ch);
+    wk.bytes = cv.off;
+    return wk;
+  }
   if (fused_grad(c, op)) return wk;
   if (fused_eloc(c, op)) {
     wk.partial = (double*)cv.take(fused_part_bytes(c) * ch);
@@ -261,8 +286,7 @@ VmcCarve vmc_carve(const nqs_ctx* c, int64_t S) {
   v.next = off; off += align_up((size_t)c->P * 16);
   v.stats = off; off += align_up(8 * 8);
   v.sub = off;
-  size_t sub = plan(c, NQS_OP_ELOC, S, nullptr).bytes;
-  sub = std::max(sub, plan(c, NQS_OP_GRAD, S, nullptr).bytes);
+  size_t sub = plan(c, NQS_OP_ELOC_GRAD, S, nullptr).bytes;
   sub = std::max(sub, sr_workspace_bytes(c, S));
   sub = std::max(sub, cg_workspace_bytes(c, S));
   v.bytes = off + align_up(std::max<size_t>(sub, 1));
@@ -462,11 +486,10 @@ nqs_status nqs_vmc_step(nqs_ctx* c, const int8_t* spins, int64_t S, double lambd
   double* stats = (double*)(base + v.stats);
   void* sub = base + v.sub;
   const size_t sub_bytes = v.bytes - v.sub;
-  nqs_status s = nqs_eloc(c, spins, S, nullptr, eloc, sub, sub_bytes, st);
+  nqs_status s = nqs_eloc_grad(c, spins, S, nullptr, eloc, O, sub, sub_bytes, st);
   if (s != NQS_OK) return s;
   hipError_t e = launch_energy_stats(eloc, S, stats, st);
   if (e != hipSuccess) return hip_fail(c, e, "energy statistics");
-  if ((s = nqs_grad(c, spins, S, O, nullptr, sub, sub_bytes, st)) != NQS_OK) return s;
   int iters = 0;
   double resid = 0.0;
   s = solver == 0 ? nqs_sr_solve(c, O, eloc, S, lambda, dtau, dth, sub, sub_bytes, st)
@@ -806,6 +829,38 @@ nqs_status nqs_grad(nqs_ctx* c, const int8_t* spins, int64_t S, void* O_out, dou
                   wide ? launch_grad_wide(c, sp, n, wk.w, (char*)O_out + (size_t)s0 * osz, st)
                        : launch_grad(c, sp, n, wk.t, wk.w, (char*)O_out + (size_t)s0 * osz, st));
     if (e != hipSuccess) return hip_fail(c, e, "grad launch");
+  }
+  return NQS_OK;
+}
+
+nqs_status nqs_eloc_grad(nqs_ctx* c, const int8_t* spins, int64_t S, double* logpsi_out,
+                         double* eloc_out, void* O_out, void* ws, size_t ws_bytes,
+                         hipStream_t st) {
+  nqs_status s = check_common(c, spins, S, ws, ws_bytes, NQS_OP_ELOC_GRAD);
+  if (s != NQS_OK) return s;
+  if (S > 0 && (!eloc_out || !O_out)) return fail(c, NQS_ERR_ARG, "eloc_out or O_out is NULL");
+  if (!shared_eloc_grad(c)) {
+    s = nqs_eloc(c, spins, S, logpsi_out, eloc_out, ws, ws_bytes, st);
+    return s == NQS_OK ? nqs_grad(c, spins, S, O_out, nullptr, ws, ws_bytes, st) : s;
+  }
+  const Work wk = plan(c, NQS_OP_ELOC_GRAD, S, ws);
+  const size_t osz = (size_t)c->P * 2 * real_size(c);
+  for (int64_t s0 = 0; s0 < S; s0 += wk.chunk) {
+    const int64_t n = std::min(wk.chunk, S - s0);
+    const int8_t* sp = spins + s0 * c->N;
+    double* lp = logpsi_out ? logpsi_out + 2 * s0 : wk.lp;
+    // E_loc and log psi, the image log amplitudes kept; then the weights and
+    // O_k from them
+    hipError_t e = NQS_RUN(c, K_ELOC, st, launch_eloc_wide(c, sp, n, wk.partial, st, wk.L));
+    if (e == hipSuccess)
+      e = NQS_RUN(c, K_ELOC_FIN, st,
+                  launch_fused_finish(c, sp, n, wk.partial, lp, eloc_out + 2 * s0, 2, st));
+    if (e == hipSuccess)
+      e = NQS_RUN(c, K_LSE, st, launch_lse(c, wk.L, n, wk.lp2, wk.w, st, true));
+    if (e == hipSuccess)
+      e = NQS_RUN(c, K_GRAD, st,
+                  launch_grad_wide(c, sp, n, wk.w, (char*)O_out + (size_t)s0 * osz, st));
+    if (e != hipSuccess) return hip_fail(c, e, "eloc_grad launch");
   }
   return NQS_OK;
 }

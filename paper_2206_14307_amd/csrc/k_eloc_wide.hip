@@ -54,7 +54,8 @@ struct WideCfg {
 
 // PAIRS: the rows are exchange neighbours with parent bonds (parent[s]); the
 // bond list is the parent's unordered-pair list and pairs counted twice weigh 2.
-template <int N, int PREC, bool PAIRS>
+// WL: also write the images' log amplitudes, unreduced (see below).
+template <int N, int PREC, bool PAIRS, bool WL>
 __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
     const int8_t* __restrict__ spins, int64_t S, const uint8_t* __restrict__ perm, int G, int K,
     int M, const typename ThetaTraits<PREC>::AFrag* __restrict__ wfrag,
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
     const int32_t* __restrict__ bonds, const int32_t* __restrict__ wmap,
     const int32_t* __restrict__ wrow,
     const double* __restrict__ chi, const float* __restrict__ Tpm, const float* __restrict__ F,
-    double* __restrict__ part, const int16_t* __restrict__ parent) {
+    double* __restrict__ part, const int16_t* __restrict__ parent, double* __restrict__ Lout) {
   using T = ThetaTraits<PREC>;
   using Cfg = WideCfg<N>;
   constexpr int NB = Cfg::NB, NK = nk_of<N, PREC>(), NSTG = Cfg::NSTG;
@@ -74,6 +75,9 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
   __shared__ __align__(16) float tx[kWideWaves][16 * kXS];
   __shared__ uint16_t list[NB];
   __shared__ int nc_s;
+  // WL: the wave's unreduced log amplitudes [RBM][image][4], held until the
+  // end of its image round (stores from the chunk loop slowed it)
+  __shared__ double lraw[WL ? kWideWaves : 1][WL ? kWideLrawK * 16 * 4 : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int q = lane >> 4, c = lane & 15;
@@ -285,6 +289,17 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
             axr += __shfl_xor(axr, 32, 64);
             axi += __shfl_xor(axi, 32, 64);
             const double Er = axr + sx + (double)E * 0.69314718055994530942;
+            if (WL && pass == 0 && q == 0) {
+              // the image's log amplitude L_kg = log(prod_h 2 cosh theta) + a x,
+              // unreduced: (Er, a x imaginary part, the joined product P) with
+              // L = Er + log|P| + i (Im a x + arg P), for a gradient pass on the
+              // same configurations (the log and arg are taken there)
+              double* o = &lraw[wv][(k * 16 + c) * 4];
+              o[0] = Er;
+              o[1] = axi;
+              o[2] = (double)pr;
+              o[3] = (double)pi;
+            }
             const double mk = wave_max(Er);
             if (mk > m_item) {
               const double sc = (double)exp_t((float)(m_item - mk));   // 0 at the first RBM
@@ -323,6 +338,13 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
       Qi = wave_sum(Qi);
       denr = wave_sum(denr);
       deni = wave_sum(deni);
+      if (WL && active) {
+        // the round's log amplitudes to [S][K][G][4]: 16 images x 4 reals per RBM
+        for (int e = lane; e < K * 64; e += 64) {
+          const int kk = e >> 6, ci = (e >> 2) & 15, j = e & 3;
+          Lout[(((size_t)s * K + kk) * G + blk * 16 + ci) * 4 + j] = lraw[wv][e];
+        }
+      }
       if (active && lane == 0) {
         double* o = part + ((size_t)s * nblk + blk) * 6;
         o[0] = m_item;
@@ -343,20 +365,24 @@ __global__ __launch_bounds__(64 * kWideWaves) void eloc_wide_kernel(
 
 template <int N, int PREC>
 hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, hipStream_t st,
-               const int16_t* parent = nullptr) {
+               const int16_t* parent, double* Lout) {
+#define NQS_WIDE_ARGS                                                                     \
+  spins, S, c->dev.perm, c->G, c->K, c->M, wf, (const float*)c->par.bias,                 \
+      (const float*)c->par.avec, c->dev.bonds, c->dev.wmap, c->dev.wrow, c->dev.chi,      \
+      (const float*)c->par.Tpm, (const float*)c->par.F, part
   const int64_t blocks = std::min<int64_t>(S, c->n_cu > 0 ? c->n_cu : 256);
   const auto* wf = (const typename ThetaTraits<PREC>::AFrag*)(PREC == kPrecF32X3 ? c->par.wfrag3
                                                                                  : c->par.wfrag);
   if (parent)
-    eloc_wide_kernel<N, PREC, true><<<(unsigned)blocks, 64 * kWideWaves, 0, st>>>(
-        spins, S, c->dev.perm, c->G, c->K, c->M, wf, (const float*)c->par.bias,
-        (const float*)c->par.avec, c->dev.bonds, c->dev.wmap, c->dev.wrow, c->dev.chi,
-        (const float*)c->par.Tpm, (const float*)c->par.F, part, parent);
+    eloc_wide_kernel<N, PREC, true, false><<<(unsigned)blocks, 64 * kWideWaves, 0, st>>>(
+        NQS_WIDE_ARGS, parent, nullptr);
+  else if (Lout)
+    eloc_wide_kernel<N, PREC, false, true><<<(unsigned)blocks, 64 * kWideWaves, 0, st>>>(
+        NQS_WIDE_ARGS, nullptr, Lout);
   else
-    eloc_wide_kernel<N, PREC, false><<<(unsigned)blocks, 64 * kWideWaves, 0, st>>>(
-        spins, S, c->dev.perm, c->G, c->K, c->M, wf, (const float*)c->par.bias,
-        (const float*)c->par.avec, c->dev.bonds, c->dev.wmap, c->dev.wrow, c->dev.chi,
-        (const float*)c->par.Tpm, (const float*)c->par.F, part, nullptr);
+    eloc_wide_kernel<N, PREC, false, false><<<(unsigned)blocks, 64 * kWideWaves, 0, st>>>(
+        NQS_WIDE_ARGS, nullptr, nullptr);
+#undef NQS_WIDE_ARGS
   return hipGetLastError();
 }
 
@@ -367,24 +393,31 @@ bool eloc_wide_supported(const nqs_ctx* c) {
   return c->N == 36 || c->N == 64 || c->N == 100;
 }
 
+namespace {
+hipError_t dispatch(const nqs_ctx* c, const int8_t* spins, int64_t S, const int16_t* parent,
+                    double* part, double* Lout, hipStream_t st) {
+  if (S <= 0) return hipSuccess;
+  const bool bf = c->prec == NQS_BF16X2;
+  switch (c->N) {
+    case 36: return bf ? run<36, NQS_BF16X2>(c, spins, S, part, st, parent, Lout)
+                       : run<36, kPrecF32X3>(c, spins, S, part, st, parent, Lout);
+    case 64: return bf ? run<64, NQS_BF16X2>(c, spins, S, part, st, parent, Lout)
+                       : run<64, kPrecF32X3>(c, spins, S, part, st, parent, Lout);
+    case 100: return bf ? run<100, NQS_BF16X2>(c, spins, S, part, st, parent, Lout)
+                        : run<100, kPrecF32X3>(c, spins, S, part, st, parent, Lout);
+    default: return hipErrorNotSupported;
+  }
+}
+}  // namespace
+
 hipError_t launch_eloc_wide(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part,
-                            hipStream_t st) {
-  return launch_eloc_wide_pairs(c, spins, S, nullptr, part, st);
+                            hipStream_t st, double* Lout) {
+  return dispatch(c, spins, S, nullptr, part, Lout, st);
 }
 
 hipError_t launch_eloc_wide_pairs(const nqs_ctx* c, const int8_t* spins, int64_t S,
                                   const int16_t* parent, double* part, hipStream_t st) {
-  if (S <= 0) return hipSuccess;
-  const bool bf = c->prec == NQS_BF16X2;
-  switch (c->N) {
-    case 36: return bf ? run<36, NQS_BF16X2>(c, spins, S, part, st, parent)
-                       : run<36, kPrecF32X3>(c, spins, S, part, st, parent);
-    case 64: return bf ? run<64, NQS_BF16X2>(c, spins, S, part, st, parent)
-                       : run<64, kPrecF32X3>(c, spins, S, part, st, parent);
-    case 100: return bf ? run<100, NQS_BF16X2>(c, spins, S, part, st, parent)
-                        : run<100, kPrecF32X3>(c, spins, S, part, st, parent);
-    default: return hipErrorNotSupported;
-  }
+  return dispatch(c, spins, S, parent, part, nullptr, st);
 }
 
 }  // namespace nqs

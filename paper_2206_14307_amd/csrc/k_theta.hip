@@ -340,22 +340,35 @@ __global__ __launch_bounds__(256) void theta_kernel(
 // Per-sample log-sum-exp over (k, g): log psi = m + log sum chi_g exp(L - m);
 // the normalised image weights w = chi_g exp(L - log psi) feed E_loc and O_k.
 // One wavefront per sample (shuffle reductions, no barriers), FP64 throughout.
-template <typename R>
+// RAW: L unreduced as the wide E_loc kernel writes it, four reals per image
+// (E, b, p, q) with L = E + log|p + i q| + i (b + arg(p + i q)).
+template <bool RAW>
+__device__ __forceinline__ double2 lse_L(const double* Ls, int i) {
+  if constexpr (RAW) {
+    const double p = Ls[4 * i + 2], q = Ls[4 * i + 3];
+    return make_double2(Ls[4 * i] + 0.5 * log(p * p + q * q), Ls[4 * i + 1] + atan2(q, p));
+  } else {
+    return make_double2(Ls[2 * i], Ls[2 * i + 1]);
+  }
+}
+
+template <typename R, bool RAW>
 __global__ __launch_bounds__(256) void lse_kernel(const double* __restrict__ L, int64_t S, int KG,
                                                   int G, const double* __restrict__ chi,
                                                   double* __restrict__ logpsi, R* __restrict__ w) {
   const int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (s >= S) return;
   const int lane = threadIdx.x & 63;
-  const double* Ls = L + (size_t)s * KG * 2;
+  const double* Ls = L + (size_t)s * KG * (RAW ? 4 : 2);
   double m = -INFINITY;
-  for (int i = lane; i < KG; i += 64) m = fmax(m, Ls[2 * i]);
+  for (int i = lane; i < KG; i += 64) m = fmax(m, lse_L<RAW>(Ls, i).x);
   m = wave_max(m);
   double sr = 0.0, si = 0.0;
   for (int i = lane; i < KG; i += 64) {
-    const double e = chi[i % G] * exp(Ls[2 * i] - m);
+    const double2 l = lse_L<RAW>(Ls, i);
+    const double e = chi[i % G] * exp(l.x - m);
     double sn, cs;
-    sincos(Ls[2 * i + 1], &sn, &cs);
+    sincos(l.y, &sn, &cs);
     sr = fma(e, cs, sr);
     si = fma(e, sn, si);
   }
@@ -370,9 +383,10 @@ __global__ __launch_bounds__(256) void lse_kernel(const double* __restrict__ L, 
   if (w) {
     R* ws = w + (size_t)s * KG * 2;
     for (int i = lane; i < KG; i += 64) {
-      const double e = chi[i % G] * exp(Ls[2 * i] - lre);
+      const double2 l = lse_L<RAW>(Ls, i);
+      const double e = chi[i % G] * exp(l.x - lre);
       double sn, cs;
-      sincos(Ls[2 * i + 1] - lim, &sn, &cs);
+      sincos(l.y - lim, &sn, &cs);
       ws[2 * i] = (R)(e * cs);
       ws[2 * i + 1] = (R)(e * sn);
     }
@@ -430,15 +444,19 @@ hipError_t launch_theta(const nqs_ctx* c, const int8_t* spins, int64_t S, double
 }
 
 hipError_t launch_lse(const nqs_ctx* c, const double* L, int64_t S, double* logpsi_out,
-                      void* w_out, hipStream_t st) {
+                      void* w_out, hipStream_t st, bool raw) {
   if (S <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((S + 3) / 4);
+  const int KG = c->K * c->G;
   if (c->prec == NQS_FP64)
-    lse_kernel<double><<<blocks, 256, 0, st>>>(L, S, c->K * c->G, c->G, c->dev.chi, logpsi_out,
-                                               (double*)w_out);
+    lse_kernel<double, false><<<blocks, 256, 0, st>>>(L, S, KG, c->G, c->dev.chi, logpsi_out,
+                                                      (double*)w_out);
+  else if (raw)
+    lse_kernel<float, true><<<blocks, 256, 0, st>>>(L, S, KG, c->G, c->dev.chi, logpsi_out,
+                                                    (float*)w_out);
   else
-    lse_kernel<float><<<blocks, 256, 0, st>>>(L, S, c->K * c->G, c->G, c->dev.chi, logpsi_out,
-                                              (float*)w_out);
+    lse_kernel<float, false><<<blocks, 256, 0, st>>>(L, S, KG, c->G, c->dev.chi, logpsi_out,
+                                                     (float*)w_out);
   return hipGetLastError();
 }
 

@@ -43,6 +43,8 @@ std::vector<int> place_fused_rows(const Geometry& geo, int row16, int cap16);
 // (tanh D of 8 hidden units, then F_+, F_-), placed the same way.
 constexpr int kWideRow16 = 5;
 constexpr int wide_cap16(int NB) { return NB * kWideRow16 + 256; }
+// RBMs whose log amplitudes the wide E_loc kernel can hand to the gradient
+constexpr int kWideLrawK = 4;
 
 // Binomial table of the Sz = 0 enumeration; false if C(N, N/2) overflows int64.
 bool sz0_binomials(int N, std::vector<uint64_t>& b, int64_t& count);
@@ -142,8 +144,9 @@ hipError_t launch_theta(const nqs_ctx* c, const int8_t* spins, int64_t S, double
                         void* t_out, hipStream_t st);
 // Per sample: log psi = LSE_{k,g}(log chi_g + L), w[s][k][g] = chi_g exp(L - log psi)
 // (complex R; skipped if w_out is null).
+// raw: L unreduced as the wide E_loc kernel writes it (four reals per image)
 hipError_t launch_lse(const nqs_ctx* c, const double* L, int64_t S, double* logpsi_out,
-                      void* w_out, hipStream_t st);
+                      void* w_out, hipStream_t st, bool raw = false);
 // Bond-exchange sums: partial[s][tile] = sum_{b anti} (J_b/2) sum_{g in tile, k} w R.
 hipError_t launch_eloc_bonds(const nqs_ctx* c, const int8_t* spins, int64_t S, const void* t,
                              const void* w, double* partial, hipStream_t st);
@@ -155,8 +158,10 @@ bool eloc_fused_supported(const nqs_ctx* c);
 bool grad_fused_supported(const nqs_ctx* c);
 hipError_t launch_enum_sz0(const nqs_ctx* c, int64_t count, int8_t* out, hipStream_t st);
 bool eloc_wide_supported(const nqs_ctx* c);
+// Lout (optional): the per-image log amplitudes [S][K][G], unreduced (four
+// reals each, see launch_lse), for a gradient pass on the same configurations
 hipError_t launch_eloc_wide(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part,
-                            hipStream_t st);
+                            hipStream_t st, double* Lout = nullptr);
 hipError_t launch_fused_finish(const nqs_ctx* c, const int8_t* spins, int64_t S,
                                const double* part, double* logpsi, double* eloc, int eloc_stride,
                                hipStream_t st);

@@ -20,10 +20,10 @@ NQS_OK, NQS_ERR_ARG, NQS_ERR_DEVICE, NQS_ERR_OOM, NQS_ERR_NONFINITE, NQS_WARN_DE
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 IRREP = {"A1": 0, "A2": 1, "B1": 2, "B2": 3}
 OP = {"logpsi": 0, "eloc": 1, "moments": 2, "grad": 3, "sr": 4, "sample": 5, "sq": 6, "vmc": 7, "cg": 8,
-      "moments2": 9}
+      "moments2": 9, "eloc_grad": 10}
 
 EXPORTS = ["nqs_create", "nqs_destroy", "nqs_num_params", "nqs_workspace_bytes", "nqs_set_params",
-           "nqs_logpsi", "nqs_eloc", "nqs_eloc_noalloc", "nqs_lanczos_moments", "nqs_lanczos_moments_p2", "nqs_grad", "nqs_sr_solve",
+           "nqs_logpsi", "nqs_eloc", "nqs_eloc_noalloc", "nqs_lanczos_moments", "nqs_lanczos_moments_p2", "nqs_grad", "nqs_eloc_grad", "nqs_sr_solve",
            "nqs_chain_init", "nqs_sample", "nqs_enumerate_sz0", "nqs_set_factor_form",
            "nqs_structure_factor", "nqs_get_params", "nqs_vmc_step", "nqs_sr_solve_cg",
            "nqs_profile_enable", "nqs_profile_read", "nqs_status_str", "nqs_last_error"]
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
         "nqs_lanczos_moments_p2": ([vp, vp, i64, C.c_int, vp, C.POINTER(Moments2), vp, C.c_size_t,
                                     vp], C.c_int),
         "nqs_grad": ([vp, vp, i64, vp, vp, vp, C.c_size_t, vp], C.c_int),
+        "nqs_eloc_grad": ([vp, vp, i64, vp, vp, vp, vp, C.c_size_t, vp], C.c_int),
         "nqs_sr_solve": ([vp, vp, vp, i64, dbl, dbl, vp, vp, C.c_size_t, vp], C.c_int),
         "nqs_chain_init": ([vp, vp, i64, u64, vp, vp], C.c_int),
         "nqs_sample": ([vp, i64, i64, i32, i32, u64, vp, vp, vp, vp, vp, C.c_size_t, vp], C.c_int),
@@ -316,6 +317,19 @@ class NQS:
         self._check(self.lib.nqs_grad(self._ctx, _ptr(sp), S, _ptr(O), _ptr(lp), _ptr(ws),
                                       ws.numel(), _stream()), "nqs_grad")
         return (O, lp) if want_logpsi else O
+
+    def eloc_grad(self, spins, want_logpsi=True):
+        """(log psi, E_loc, O) of the same configurations in one call
+        (nqs_eloc_grad); (E_loc, O) without log psi."""
+        sp = self._spins(spins)
+        S = sp.shape[0]
+        el = torch.empty(S, dtype=torch.complex128, device=self.device)
+        lp = torch.empty(S, dtype=torch.complex128, device=self.device) if want_logpsi else None
+        O = torch.empty((S, self.P), dtype=self.o_dtype, device=self.device)
+        ws = self.workspace("eloc_grad", S)
+        self._check(self.lib.nqs_eloc_grad(self._ctx, _ptr(sp), S, _ptr(lp), _ptr(el), _ptr(O),
+                                           _ptr(ws), ws.numel(), _stream()), "nqs_eloc_grad")
+        return (lp, el, O) if want_logpsi else (el, O)
 
     def sr_solve(self, O, eloc, lam=1e-6, dtau=0.01):
         S = O.shape[0]

@@ -12,7 +12,11 @@ configuration, seconds per row at 8x8 and 10x10).
   (O rows against the oracle's log-derivatives);
 * 8x8 K = 4 Lanczos moments: e1 and e2 against the oracle values stored by
   tests/golden/make_e2_8x8.py, on their own and planted in the 16 384-configuration launch;
-* 10x10 M = 400, 32 768 configurations: nqs_eloc, nqs_grad and nqs_logpsi (split BF16).
+* 10x10 M = 400, 32 768 configurations: nqs_eloc, nqs_grad and nqs_logpsi (split BF16);
+* nqs_eloc_grad (the benchmark step in one call) at 10x10 full size, and on 2048
+  configurations of the 8x8 K = 4 FP32 and 6x6 M = 72 models: log psi and E_loc
+  equal nqs_eloc's bit for bit, O equals nqs_grad's to rounding, sampled rows
+  match the oracle.
 """
 import dataclasses
 import json
@@ -158,3 +162,39 @@ def test_lanczos_moments_8x8_full_size():
     diag = 0.25 * float((J * s[bonds[:, 0]] * s[bonds[:, 1]]).sum())
     e2 = diag * e12[r, 0] + (0.5 * J[anti] * np.exp(lpn - lp0) * eln).sum()
     assert abs(e12[r, 1] - e2) <= TOL[w.precision] * max(1.0, abs(e2)), (e12[r, 1], e2)
+
+
+@pytest.mark.parametrize("name,over,S", [("10x10_m400", {}, None),
+                                         ("8x8_k4_m256", {"precision": "fp32"}, 2048),
+                                         ("6x6_fp32_eloc", {}, 2048)])
+def test_eloc_grad_one_call(name, over, S):
+    """nqs_eloc_grad against nqs_eloc + nqs_grad and the oracle.  The wide
+    models (10x10, 8x8) take the gradient's image weights from the log
+    amplitudes of the E_loc pass instead of a theta pass; the 6x6 model runs
+    the two calls."""
+    w, p, m, sp, rows, om = _setup(name, **over)
+    if S is not None:
+        sp = np.ascontiguousarray(sp[:S])
+        rows = np.r_[0, S - 1, 17]
+    rows = rows[nonzero_rows(om, p, sp[rows])][:2]
+    tol = TOL[w.precision]
+    spt = torch.from_numpy(sp).cuda()
+    lp, el, O = m.eloc_grad(spt)
+    lp2, el2 = m.eloc(spt)
+    assert torch.equal(lp, lp2) and torch.equal(el, el2)
+    del lp2, el2
+    sel = torch.from_numpy(rows).cuda()
+    Os = O[sel].cpu().numpy()
+    # all rows against nqs_grad, in slices (O is 10.6 GB at 10x10)
+    worst = 0.0
+    for a in range(0, len(sp), 4096):
+        Ob = m.grad(spt[a:a + 4096])
+        d = torch.linalg.vector_norm(O[a:a + 4096] - Ob, dim=1) / torch.linalg.vector_norm(Ob, dim=1)
+        worst = max(worst, float(d.max()))
+        del Ob, d
+    del O
+    print(f"{name}: max row-relative |O - O(nqs_grad)| {worst:.3g}")
+    assert worst < tol
+    assert max_rel_err(el.cpu().numpy()[rows], oracle.eloc_direct(om, p, sp[rows])) < tol
+    assert max_logpsi_err(lp.cpu().numpy()[rows], oracle.logpsi(om, p, sp[rows])) < tol
+    assert max_row_rel_err(Os, oracle.logderiv(om, p, sp[rows])) < tol
