@@ -5,9 +5,10 @@ Workload (default): the 10x10 J1-J2 lattice (J2/J1 = 0.5), one complex RBM
 with M = 400 (alpha = 4), theta on split hi+lo BF16 MFMA with FP32
 accumulation, projected on the 800 space-group images; 1024 exchange-
 Metropolis chains x 32 samples = 32 768 configurations drawn by nqs_sample
-and resident in HBM.  A step is nqs_eloc (log psi + E_loc) followed by
-nqs_grad (O_k = d log psi / d theta_k for W, a, b) over the whole batch;
-value = S * K * G / step time.
+and resident in HBM.  A step is one nqs_eloc_grad call over the whole batch:
+log psi, E_loc and O_k = d log psi / d theta_k for W, a, b (the gradient's
+image weights from the log amplitudes of the E_loc pass); value =
+S * K * G / step time.
 
 Printed as ONE JSON line, with
   roofline     -- the dominant kernel (the wide E_loc kernel): achieved
