@@ -18,8 +18,9 @@ import pytest
 import torch
 
 import oracle
-from helpers import (TOL, grad_error_scale, logpsi_error_scale, max_logpsi_err, max_row_rel_err,
-                     max_scaled_logpsi_err, max_scaled_row_err, nonzero_rows, stress_params)
+from helpers import (TOL, grad_error_scale, logpsi_error_scale, max_logpsi_err, max_rel_err,
+                     max_row_rel_err, max_scaled_logpsi_err, max_scaled_row_err, nonzero_rows,
+                     stress_params)
 from workloads import WORKLOADS, draw_params, random_sz0_spins
 
 pytestmark = pytest.mark.gpu
@@ -165,3 +166,32 @@ def test_logpsi_autograd_function(case):
     with torch.no_grad():
         lp2 = LogPsi.apply(pt.detach(), cuda(sp), m)
     assert max_logpsi_err(lp2.cpu().numpy(), lp.detach().cpu().numpy()) < tol
+
+
+@pytest.mark.parametrize("name,over", [("6x6_fp32_eloc", {"n_hidden": 144}),
+                                       ("6x6_fp32_eloc", {"n_rbm": 8, "n_hidden": 24})])
+def test_eloc_grad_edges(name, over):
+    """nqs_eloc_grad on a wide model sharing the log amplitudes (K = 1, M = 144)
+    and on one beyond the shared path (K = 8 > 4 RBMs: nqs_eloc, then nqs_grad):
+    no configurations, a single one against the oracle, a too-small workspace."""
+    from paper_2206_14307_amd.nqs import NQSError, _ptr, _stream
+    w = dataclasses.replace(WORKLOADS[name], **over)
+    p = draw_params(w)
+    om = oracle.Model.from_workload(w)
+    m = make(w, p)
+    sp = random_sz0_spins(w.N, 3, 9)
+    lp, el, O = m.eloc_grad(cuda(sp[:0]))
+    assert el.numel() == 0 and O.numel() == 0
+    lp, el, O = m.eloc_grad(cuda(sp))
+    tol = TOL[w.precision]
+    assert max_rel_err(el.cpu().numpy(), oracle.eloc_direct(om, p, sp)) < tol
+    assert max_row_rel_err(O.cpu().numpy(), oracle.logderiv(om, p, sp)) < tol
+    lp2, el2 = m.eloc(cuda(sp))
+    assert torch.equal(lp, lp2) and torch.equal(el, el2)
+    need = int(m.lib.nqs_workspace_bytes(m._ctx, 10, 3))
+    ws = torch.empty(max(need // 2, 1), dtype=torch.uint8, device="cuda")
+    spt = cuda(sp)
+    st = m.lib.nqs_eloc_grad(m._ctx, _ptr(spt), 3, None, _ptr(el), _ptr(O), _ptr(ws), ws.numel(),
+                             _stream())
+    with pytest.raises(NQSError, match="workspace too small"):
+        m._check(st, "nqs_eloc_grad")
