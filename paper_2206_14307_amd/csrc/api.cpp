@@ -242,7 +242,7 @@ hipError_t prep_tables(nqs_ctx* c, hipStream_t st) {
 void free_all(nqs_ctx* c) {
   void* ptrs[] = {c->dev.perm, c->dev.perminv, c->dev.bonds, c->dev.bond_J, c->dev.bmap, c->dev.chi,
                   c->dev.fmap, c->dev.frow, c->dev.wmap, c->dev.wrow, c->dev.binom,
-                  c->par.params, c->par.wfrag, c->par.wfrag3, c->par.bias, c->par.avec, c->par.Tpm,
+                  c->par.params, c->par.wfrag, c->par.wfrag3, c->par.wfrag_s3, c->par.bias, c->par.avec, c->par.Tpm,
                   c->par.F, c->par.Tpair, c->par.Fpair, c->par.Tdir, c->par.Urec, c->par.flag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -396,15 +396,21 @@ nqs_status nqs_create(const nqs_model_desc* d, nqs_ctx** out) {
   }
   const size_t rs = real_size(c);
   const size_t frag_bytes = (size_t)c->n_htiles * c->nk * 64 * (c->prec == NQS_BF16X2 ? 16 : rs);
-  // FP32 models: theta of the fused gradient kernel from a three-term BF16 split of W
+  // FP32 models: theta from a three-term BF16 split of W, with the K axis as
+  // [W_hi | W_mid | W_lo | 0] (E_loc, wide gradient and theta kernels) and
+  // grouped by site (fused gradient kernel)
   const size_t frag3_bytes =
       c->prec == NQS_FP32 ? (size_t)c->n_htiles * ((3 * c->N + 31) / 32) * 64 * 16 : 0;
+  const size_t frag_s3_bytes = c->prec == NQS_FP32 && grad_fused_supported(c)
+                                   ? (size_t)c->n_htiles * ((3 * (c->N / 4) + 7) / 8) * 64 * 16
+                                   : 0;
   struct {
     void** p;
     size_t n;
   } allocs[] = {{(void**)&c->par.params, (size_t)c->P * 16},
                 {&c->par.wfrag, frag_bytes},
                 {&c->par.wfrag3, frag3_bytes},
+                {&c->par.wfrag_s3, frag_s3_bytes},
                 {&c->par.bias, (size_t)c->KM * 2 * rs},
                 {&c->par.avec, (size_t)c->K * c->N * 2 * rs},
                 {&c->par.Tpm, (size_t)c->NB * 2 * c->KM * 2 * rs},

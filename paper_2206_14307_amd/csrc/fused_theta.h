@@ -24,7 +24,8 @@ __device__ __forceinline__ void theta_block(
     const int8_t* srow,
     const uint8_t* prow, int lane, typename ThetaTraits<PREC>::R* tr,
     typename ThetaTraits<PREC>::R* ti, double* Er, typename ThetaTraits<PREC>::R* Pr,
-    typename ThetaTraits<PREC>::R* Pi, typename ThetaTraits<PREC>::R* Ai) {
+    typename ThetaTraits<PREC>::R* Pi, typename ThetaTraits<PREC>::R* Ai,
+    const float* axp = nullptr) {
   using T = ThetaTraits<PREC>;
   using R = typename T::R;
   constexpr int NK = nk_of<N, PREC>();
@@ -57,7 +58,11 @@ __device__ __forceinline__ void theta_block(
     // a . (g sigma): FP32 / FP64 fragments hold x_j for j = q mod 4
     R xr = R(0), xi = R(0);
     const R* ak = avec + (size_t)k * N * 2;
-    if constexpr (!bf16_mfma(PREC)) {
+    if constexpr (PREC == kPrecF32S3) {
+      // the caller's partial sums over the lane's sites 4i + q
+      xr = axp[2 * k];
+      xi = axp[2 * k + 1];
+    } else if constexpr (!bf16_mfma(PREC)) {
 #pragma unroll
       for (int kk = 0; kk < NK; ++kk) {
         xr = fmaf_t(bx[kk], ak[2 * (4 * kk + q)], xr);

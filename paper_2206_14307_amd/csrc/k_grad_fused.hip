@@ -1,6 +1,8 @@
 // Fused log-derivatives O_k = d log psi / d theta_k (Sec. 3.2, below
 // Eq. (12)) for models whose hidden layer fits one wavefront (K*M <= 128),
-// with theta computed in FP32 or split BF16 and everything else in FP32.
+// with theta of FP32 models on BF16 MFMA from the exact site-grouped
+// three-term split of W (FP32 products, FP32 accumulation), of BF16X2 models
+// in split BF16, and everything else in FP32.
 //
 // With u_kg = chi_g psi_s^(k)(g sigma) / e^m (any common shift m), the image
 // x_g = g sigma and t = tanh(theta):
@@ -38,15 +40,17 @@ struct GradCfg {
   static constexpr int KM = K * M;
   static constexpr int NHT = KM / 8;             // hidden tiles: 8 units = 16 B columns
   static constexpr int NCT = NHT + 1;            // + the u tile (2K columns)
+  static_assert(2 * K <= 4, "the u columns live in the 4 padding floats of a tile row");
   static constexpr int NST = (N + 1 + 15) / 16;  // site tiles incl. the ones row
   static constexpr int NK = nk_of<N, PREC>();
   // one 16 x 16 tile, rows (images) 20 floats apart: the contraction's reads
-  // of rows 4q + r by the four lane groups q fall on disjoint bank groups
+  // of rows 4q + r by the four lane groups q fall on disjoint bank groups.
+  // Floats 16 .. 19 of a row of tile 0 hold the u columns (Re u_k, Im u_k).
   static constexpr int TR = 20;
   static constexpr int TS = 16 * TR;
   static constexpr int XQ = 4 * 16 * NST;        // image words: [q][site] incl. ones + zeros
   static constexpr size_t LDS = (size_t)NHT * NK * 64 * sizeof(typename T::AFrag) +
-                                (size_t)kGradWaves * NCT * TS * sizeof(float) +
+                                (size_t)kGradWaves * NHT * TS * sizeof(float) +
                                 (size_t)kGradWaves * XQ * 16 +
                                 (size_t)(2 * KM + 2 * K * N) * sizeof(float);
 };
@@ -70,7 +74,7 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
   constexpr int TR = Cfg::TR, XQ = Cfg::XQ;
   constexpr int TPR = M / 8;
   __shared__ __align__(16) AF Wl[NHT * NK * 64];
-  __shared__ float tb[kGradWaves][NCT * TS];
+  __shared__ float tb[kGradWaves][NHT * TS];
   // the block's images as BF16 words [q][site]: x of images 4q .. 4q+3, twice
   __shared__ __align__(16) uint4 xq[kGradWaves][XQ];
   __shared__ float bl[2 * Cfg::KM], al[2 * K * N];   // hidden and visible biases
@@ -80,7 +84,6 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
   for (int idx = threadIdx.x; idx < 2 * K * N; idx += blockDim.x) al[idx] = avec[idx];
   const int lane0 = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float* tw = tb[wv];
-  for (int idx = lane0; idx < TS; idx += 64) tw[NHT * TS + idx] = 0.f;   // unused u columns
   uint4* xw = xq[wv];
   for (int idx = lane0; idx < 4 * (16 * NST - N); idx += 64) {            // ones row, zero pad
     const int qq = idx / (16 * NST - N), j = N + idx % (16 * NST - N);
@@ -109,11 +112,32 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
       const int g = blk * 16 + c;
       const uint8_t* prow = perm + (size_t)g * N;
       typename T::BFrag bx[NK];
-      load_bfrag<N, PREC>(srow, prow, q, bx);
       // image c into the contraction's A words: BF16 x at slots c % 4 and c % 4 + 4
       // of word (c / 4, site)
       unsigned short* xh = reinterpret_cast<unsigned short*>(xw) + (c >> 2) * 16 * NST * 8 + (c & 3);
-      if constexpr (bf16_mfma(PREC)) {
+      float axp[2 * K];   // site-grouped form: this lane's partial sums of a . x
+      if constexpr (PREC == kPrecF32S3) {
+        float xv[N / 4];
+        uint32_t dx[N / 4];
+        load_bfrag_s3<N>(srow, prow, q, bx, xv, dx);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          float xr = 0.f, xi = 0.f;
+#pragma unroll
+          for (int i = 0; i < N / 4; ++i) {
+            xr = fmaf(xv[i], al[2 * (k * N + 4 * i + q)], xr);
+            xi = fmaf(xv[i], al[2 * (k * N + 4 * i + q) + 1], xi);
+          }
+          axp[2 * k] = xr;
+          axp[2 * k + 1] = xi;
+        }
+#pragma unroll
+        for (int i = 0; i < N / 4; ++i) {
+          xh[(4 * i + q) * 8] = (unsigned short)dx[i];
+          xh[(4 * i + q) * 8 + 4] = (unsigned short)dx[i];
+        }
+      } else if constexpr (bf16_mfma(PREC)) {
+        load_bfrag<N, PREC>(srow, prow, q, bx);
 #pragma unroll
         for (int kk = 0; kk < NK; ++kk) {
           // the fragment's BF16 pairs as words, halves taken with integer shifts
@@ -130,6 +154,7 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
           }
         }
       } else {
+        load_bfrag<N, PREC>(srow, prow, q, bx);
 #pragma unroll
         for (int kk = 0; kk < NK; ++kk) {
           const unsigned short h = (unsigned short)(__float_as_uint((float)bx[kk]) >> 16);
@@ -139,7 +164,7 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
       }
       float tr[NHT * 2], ti[NHT * 2], Pr[K], Pi[K], Ai[K];
       double Er[K];
-      theta_block<N, PREC, K, M>(Wl, bx, bl, al, srow, prow, lane, tr, ti, Er, Pr, Pi, Ai);
+      theta_block<N, PREC, K, M>(Wl, bx, bl, al, srow, prow, lane, tr, ti, Er, Pr, Pi, Ai, axp);
 
       double mloc = Er[0];
 #pragma unroll
@@ -180,8 +205,8 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
       if (q == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          tw[NHT * TS + c * TR + 2 * k] = ur[k];
-          tw[NHT * TS + c * TR + 2 * k + 1] = ui[k];
+          tw[c * TR + 16 + 2 * k] = ur[k];
+          tw[c * TR + 16 + 2 * k + 1] = ui[k];
         }
       }
       wave_sync_lds();
@@ -190,8 +215,18 @@ __global__ __launch_bounds__(64 * kGradWaves) void grad_fused_kernel(
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) {
         float v[4];
+        if (ct < NHT) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = tw[ct * TS + (4 * q + r) * TR + c];
+          for (int r = 0; r < 4; ++r) v[r] = tw[ct * TS + (4 * q + r) * TR + c];
+        } else {
+          // the u tile: columns 0 .. 2K-1 from the padding of tile 0, the rest zero
+          const int cu = c < 2 * K ? c : 2 * K - 1;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float u = tw[(4 * q + r) * TR + 16 + cu];
+            v[r] = c < 2 * K ? u : 0.f;
+          }
+        }
         bf16x8 b1, b2;
         split3_bf16(v, b1, b2);
 #pragma unroll
@@ -282,8 +317,10 @@ hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, void* O, double
                hipStream_t st) {
   int64_t blocks = (S + kGradWaves - 1) / kGradWaves;
   blocks = std::min<int64_t>(blocks, 2 * (int64_t)(c->n_cu > 0 ? c->n_cu : 256));
+  const void* wf = PREC == kPrecF32S3 ? c->par.wfrag_s3 : c->par.wfrag;
+  if (!wf) return hipErrorInvalidValue;
   grad_fused_kernel<N, PREC, K, M><<<(unsigned)blocks, 64 * kGradWaves, 0, st>>>(
-      spins, S, c->dev.perm, c->G, (const typename ThetaTraits<PREC>::AFrag*)c->par.wfrag,
+      spins, S, c->dev.perm, c->G, (const typename ThetaTraits<PREC>::AFrag*)wf,
       (const float*)c->par.bias, (const float*)c->par.avec, c->dev.chi, c->d.use_bias, c->P_rbm,
       c->P, (float*)O, logpsi);
   return hipGetLastError();
@@ -292,10 +329,8 @@ hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, void* O, double
 template <int N, int K, int M>
 hipError_t run_prec(const nqs_ctx* c, const int8_t* spins, int64_t S, void* O, double* logpsi,
                     hipStream_t st) {
-  // theta of FP32 models stays on FP32 MFMA here: the three-term BF16 form
-  // (larger W fragments in LDS) measured slower in this kernel, 24.2 ms
-  // against 20.3 ms at 6x6 M = 72
-  return c->prec == NQS_FP32 ? run<N, NQS_FP32, K, M>(c, spins, S, O, logpsi, st)
+  // theta of FP32 models on BF16 MFMA in the site-grouped three-term form
+  return c->prec == NQS_FP32 ? run<N, kPrecF32S3, K, M>(c, spins, S, O, logpsi, st)
                              : run<N, NQS_BF16X2, K, M>(c, spins, S, O, logpsi, st);
 }
 

@@ -112,6 +112,42 @@ __global__ void prep_wfrag_x3_kernel(const double2* p, int Prbm, int M, int N, i
   }
 }
 
+// FP32 models, fused gradient kernel: the same three terms with the K slots
+// grouped by site.  Lane l = (q, c) of MFMA m holds, at slot e, row 16 ht + c
+// and flat slot f = 8 m + e of lane group q: hi (f even) or mid (f odd) of site
+// 4 (f / 2) + q for f < 2 N/4, lo of site 4 (f - 2 N/4) + q for f < 3 N/4, else
+// zero.  N is a multiple of 4.
+__global__ void prep_wfrag_s3_kernel(const double2* p, int Prbm, int M, int N, int n_htiles,
+                                     int nm, unsigned short* out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)n_htiles * nm * 64;
+  if (idx >= total) return;
+  const int l = idx % 64, mm = (idx / 64) % nm, ht = idx / (64 * nm);
+  const int row = 16 * ht + (l % 16), q = l / 16, ni = N / 4;
+  for (int e = 0; e < 8; ++e) {
+    const int f = 8 * mm + e;
+    int i = -1, term = 0;
+    if (f < 2 * ni) {
+      i = f / 2;
+      term = f & 1;
+    } else if (f < 3 * ni) {
+      i = f - 2 * ni;
+      term = 2;
+    }
+    unsigned short v = 0;
+    if (i >= 0) {
+      const double2 w = Wval(p, Prbm, M, N, row / 2, 4 * i + q);
+      const float wf = (float)((row & 1) ? w.y : w.x);
+      const float hi = __uint_as_float(__float_as_uint(wf) & 0xffff0000u);
+      const float r1 = wf - hi;
+      const float mid = __uint_as_float(__float_as_uint(r1) & 0xffff0000u);
+      const float part = term == 0 ? hi : term == 1 ? mid : r1 - mid;
+      v = (unsigned short)(__float_as_uint(part) >> 16);
+    }
+    out[idx * 8 + e] = v;
+  }
+}
+
 template <typename R>
 __global__ void prep_bias_kernel(const double2* p, int Prbm, int K, int M, int N, int use_bias,
                                  R* bias, R* avec) {
@@ -347,6 +383,12 @@ hipError_t prep_typed(const nqs_ctx* c, hipStream_t st) {
     const int64_t nf3 = (int64_t)c->n_htiles * nk3 * 64;
     prep_wfrag_x3_kernel<<<(nf3 + 255) / 256, 256, 0, st>>>(
         p, c->P_rbm, c->M, c->N, c->n_htiles, nk3, (unsigned short*)c->par.wfrag3);
+  }
+  if (c->par.wfrag_s3) {
+    const int nm = (3 * (c->N / 4) + 7) / 8;
+    const int64_t nfs = (int64_t)c->n_htiles * nm * 64;
+    prep_wfrag_s3_kernel<<<(nfs + 255) / 256, 256, 0, st>>>(
+        p, c->P_rbm, c->M, c->N, c->n_htiles, nm, (unsigned short*)c->par.wfrag_s3);
   }
   const int nb = (std::max(c->K * c->M, c->K * c->N) + 255) / 256;
   prep_bias_kernel<R><<<nb, 256, 0, st>>>(p, c->P_rbm, c->K, c->M, c->N, c->d.use_bias,

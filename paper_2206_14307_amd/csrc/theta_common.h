@@ -40,13 +40,27 @@ template <> struct ThetaTraits<kPrecF32X3> {
   using BFrag = bf16x8;
   using AFrag = bf16x8;
 };
+// Internal precision tag: the same three-term split with the K slots grouped
+// by site.  Lane group q (lanes 16q .. 16q+15) owns sites 4i + q, i < N/4; its
+// slots, taken eight per MFMA, are hi and mid of each of its sites in turn,
+// then lo of each, then zeros.  A lane then needs x of only N/4 sites (as for
+// the 16x16x4 FP32 MFMA) instead of one per slot, and the MFMA count per tile
+// is ceil(3 N/4 / 8) (4 at N = 36, against 9 FP32 MFMAs of twice the cycles).
+constexpr int kPrecF32S3 = 17;
+template <> struct ThetaTraits<kPrecF32S3> {
+  using R = float;
+  using Acc = f32x4;
+  using BFrag = bf16x8;
+  using AFrag = bf16x8;
+};
 // theta runs on 16x16x32 BF16 MFMA; copies of x along the K axis
 __host__ __device__ constexpr bool bf16_mfma(int prec) {
-  return prec == NQS_BF16X2 || prec == kPrecF32X3;
+  return prec == NQS_BF16X2 || prec == kPrecF32X3 || prec == kPrecF32S3;
 }
 __host__ __device__ constexpr int x_copies(int prec) { return prec == kPrecF32X3 ? 3 : 2; }
 
 template <int N, int PREC> constexpr int nk_of() {
+  if constexpr (PREC == kPrecF32S3) return (3 * (N / 4) + 7) / 8;
   return bf16_mfma(PREC) ? (x_copies(PREC) * N + 31) / 32 : N / 4;
 }
 
@@ -163,6 +177,44 @@ __device__ __forceinline__ SpinBits load_bfrag(const int8_t* srow, const uint8_t
     for (int kk = 0; kk < NK; ++kk) bx[kk] = (R)__uint_as_float(x_bits<N>(m, prow[4 * kk + q]));
   }
   return m;
+}
+
+// B-operand fragments of the site-grouped three-term form (kPrecF32S3) for
+// lane (q, c), image c: dword d of MFMA m covers flat slots 8m + 2d and
+// 8m + 2d + 1 of lane group q, i.e. (x_i, x_i) for the hi / mid pair of its
+// site i, or (x_i, x_i+1) in the lo run.  Also returns, per site 4i + q of the
+// lane, x as FP32 (xv) and as a BF16 pair (dx: the same BF16 value in both
+// halves).  N must be a multiple of 4.
+template <int N>
+__device__ __forceinline__ void load_bfrag_s3(const int8_t* srow, const uint8_t* prow, int q,
+                                              bf16x8* bx, float* xv, uint32_t* dx) {
+  static_assert(N % 4 == 0, "site-grouped fragments need N divisible by 4");
+  constexpr int NI = N / 4, NM = nk_of<N, kPrecF32S3>();
+  const SpinBits m = spin_bits<N>(srow);
+  uint32_t bits[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    bits[i] = x_bits<N>(m, prow[4 * i + q]);
+    xv[i] = __uint_as_float(bits[i]);
+    dx[i] = __builtin_amdgcn_perm(bits[i], bits[i], 0x03020302u);
+  }
+#pragma unroll
+  for (int mm = 0; mm < NM; ++mm) {
+    uint32_t w[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int f = 8 * mm + 2 * d;
+      if (f < 2 * NI) {
+        w[d] = dx[f / 2];
+      } else if (f < 3 * NI) {
+        const int i = f - 2 * NI;
+        w[d] = i + 1 < NI ? pack_hi16(bits[i], bits[i + 1]) : bits[i] >> 16;
+      } else {
+        w[d] = 0u;
+      }
+    }
+    bx[mm] = __builtin_bit_cast(bf16x8, w);
+  }
 }
 
 // The same fragments gathered byte by byte from the spin row (measured faster
