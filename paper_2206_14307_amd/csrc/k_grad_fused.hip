@@ -15,8 +15,9 @@
 // fused E_loc kernel); the weights use a running maximum m of Re L over the
 // blocks seen so far (the accumulators are rescaled by e^{m_old - m_new}
 // when it grows).  The products u t go through a 16 x 16 LDS tile per hidden
-// tile into the B operand of a second MFMA contraction over the images, whose
-// A operand is the gathered image x with an extra all-ones row:
+// tile (u itself through the row padding of the first tile) into the B
+// operand of a second MFMA contraction over the images, whose A operand is
+// the gathered image x with an extra all-ones row:
 //   C[j][col] = sum_g A[j][g] B[g][col],  A = [x_g | 1],  B = [Re u t | Im u t | u],
 // so the ones row gives O_b and D, and the u columns give O_a.  The
 // contraction runs on 16x16x32 BF16 MFMA with each FP32 value of B split
