@@ -146,14 +146,33 @@ __global__ __launch_bounds__(64 * kFusedWaves) void eloc_fused_kernel(
     const int8_t* srow = spins + s * N;
     const uint8_t* prow = perm + (size_t)g * N;
     typename T::BFrag bx[NK];
-    load_bfrag<N, PREC>(srow, prow, q, bx);
+    float axp[2 * K];   // site-grouped form: this lane's partial sums of a . x
+    if constexpr (PREC == kPrecF32S3) {
+      float xv[N / 4];
+      uint32_t dx[N / 4];
+      load_bfrag_s3<N>(srow, prow, q, bx, xv, dx);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        float xr = 0.f, xi = 0.f;
+#pragma unroll
+        for (int i = 0; i < N / 4; ++i) {
+          xr = fmaf(xv[i], avec[2 * (k * N + 4 * i + q)], xr);
+          xi = fmaf(xv[i], avec[2 * (k * N + 4 * i + q) + 1], xi);
+        }
+        axp[2 * k] = xr;
+        axp[2 * k + 1] = xi;
+      }
+    } else {
+      load_bfrag<N, PREC>(srow, prow, q, bx);
+    }
     const int nc = fused_list(srow, bonds, NB, list, lane);
 
     // ---- theta on MFMA + epilogue: tanh(theta) stays in registers
     R tr[NHT * 2], ti[NHT * 2];
     double Er[K];
     R Pr_[K], Pi_[K], Ai_[K];
-    theta_block<N, PREC, K, M>(Wl, bx, bias, avec, srow, prow, lane, tr, ti, Er, Pr_, Pi_, Ai_);
+    theta_block<N, PREC, K, M>(Wl, bx, bias, avec, srow, prow, lane, tr, ti, Er, Pr_, Pi_, Ai_,
+                               axp);
     // u_kg = chi_g exp(L_kg - m) = chi_g e^{Er - m} P e^{i Im a.x}; any common
     // shift m works, the largest Er keeps every u below 4 in magnitude
     double mloc = Er[0];
@@ -334,7 +353,9 @@ hipError_t run(const nqs_ctx* c, const int8_t* spins, int64_t S, double* part, d
   blocks = std::min<int64_t>(blocks, c->n_cu > 0 ? c->n_cu : 256);
   eloc_fused_kernel<N, PREC, K, M, RECIP><<<(unsigned)blocks, 64 * kFusedWaves, 0, st>>>(
       spins, S, c->dev.perm, c->G,
-      (const typename T::AFrag*)(PREC == kPrecF32X3 ? c->par.wfrag3 : c->par.wfrag),
+      (const typename T::AFrag*)(PREC == kPrecF32X3   ? c->par.wfrag3
+                                 : PREC == kPrecF32S3 ? c->par.wfrag_s3
+                                                      : c->par.wfrag),
       (const R*)c->par.bias,
       (const R*)c->par.avec, c->dev.bonds, c->dev.fmap, c->dev.frow, c->dev.chi,
       (const R*)(RECIP ? c->par.Urec : c->par.Tdir), part);
@@ -369,8 +390,11 @@ hipError_t run_prec(const nqs_ctx* c, const int8_t* spins, int64_t S, double* pa
   switch (c->prec) {
     case NQS_FP64: return run_if_fits<N, NQS_FP64, K, M>(c, spins, S, part, logpsi, eloc, es, st);
     case NQS_FP32:
-      // theta from the three-term BF16 split of W where its fragments fit in LDS
-      if constexpr (FusedCfg<N, kPrecF32X3, K, M, false>::LDS <= kLdsLimit)
+      // theta from the three-term BF16 split of W (site-grouped) where its
+      // fragments fit in LDS
+      if constexpr (N % 4 == 0 && FusedCfg<N, kPrecF32S3, K, M, false>::LDS <= kLdsLimit)
+        return run_if_fits<N, kPrecF32S3, K, M>(c, spins, S, part, logpsi, eloc, es, st);
+      else if constexpr (FusedCfg<N, kPrecF32X3, K, M, false>::LDS <= kLdsLimit)
         return run_if_fits<N, kPrecF32X3, K, M>(c, spins, S, part, logpsi, eloc, es, st);
       else
         return run_if_fits<N, NQS_FP32, K, M>(c, spins, S, part, logpsi, eloc, es, st);

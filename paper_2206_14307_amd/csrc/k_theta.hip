@@ -173,7 +173,14 @@ __global__ __launch_bounds__(256) void theta_kernel(
       live[b] = wave * CB + b < total_cb;
       s_of[b] = live[b] ? sc : 0;
       g_of[b] = (live[b] ? gb : 0) * 16 + c;
-      sb[b] = load_bfrag<N, PREC>(spins + s_of[b] * N, perm + (size_t)g_of[b] * N, q, bx[b]);
+      if constexpr (PREC == kPrecF32S3) {
+        float xv[N / 4];
+        uint32_t dx[N / 4];
+        sb[b] = load_bfrag_s3<N>(spins + s_of[b] * N, perm + (size_t)g_of[b] * N, q, bx[b], xv,
+                                 dx);
+      } else {
+        sb[b] = load_bfrag<N, PREC>(spins + s_of[b] * N, perm + (size_t)g_of[b] * N, q, bx[b]);
+      }
       if (++gb == cb_per_s) {
         gb = 0;
         ++sc;
@@ -401,7 +408,10 @@ hipError_t theta_for(const nqs_ctx* c, const int8_t* spins, int64_t S, double* L
   // column blocks per wave: 4 for FP32 / FP64 at N <= 36, otherwise 2 (fewer
   // live registers where the fragments or the MFMA chains are longer)
   constexpr int CB = (N <= 36 && !bf16_mfma(PREC)) ? 4 : 2;
-  const void* wf = PREC == kPrecF32X3 ? c->par.wfrag3 : c->par.wfrag;
+  const void* wf = PREC == kPrecF32X3   ? c->par.wfrag3
+                   : PREC == kPrecF32S3 ? c->par.wfrag_s3
+                                        : c->par.wfrag;
+  if (!wf) return hipErrorInvalidValue;
   const int64_t total_cb = S * (c->G / 16);
   const int64_t waves = (total_cb + CB - 1) / CB;
   const int64_t blocks = (waves + 3) / 4;
@@ -421,11 +431,12 @@ hipError_t theta_prec(const nqs_ctx* c, const int8_t* spins, int64_t S, double* 
                       hipStream_t st) {
   switch (c->prec) {
     case NQS_FP64: return theta_for<N, NQS_FP64>(c, spins, S, Lout, t_out, st);
-    // FP32 models: theta from the three-term BF16 split of W (FP32 numerics)
-    // up to 6x6; beyond, its longer fragment chains cost occupancy (the
-    // pipelined tile loop holds two tiles' fragments)
+    // FP32 models: theta from the three-term BF16 split of W (FP32 numerics),
+    // site-grouped, up to 6x6; beyond, its longer fragment chains cost
+    // occupancy (the pipelined tile loop holds two tiles' fragments)
     case NQS_FP32:
-      if constexpr (N <= 36) return theta_for<N, kPrecF32X3>(c, spins, S, Lout, t_out, st);
+      if constexpr (N <= 36 && N % 4 == 0) return theta_for<N, kPrecF32S3>(c, spins, S, Lout, t_out, st);
+      else if constexpr (N <= 36) return theta_for<N, kPrecF32X3>(c, spins, S, Lout, t_out, st);
       else return theta_for<N, NQS_FP32>(c, spins, S, Lout, t_out, st);
     default: return theta_for<N, NQS_BF16X2>(c, spins, S, Lout, t_out, st);
   }

@@ -184,10 +184,10 @@ __device__ __forceinline__ SpinBits load_bfrag(const int8_t* srow, const uint8_t
 // 8m + 2d + 1 of lane group q, i.e. (x_i, x_i) for the hi / mid pair of its
 // site i, or (x_i, x_i+1) in the lo run.  Also returns, per site 4i + q of the
 // lane, x as FP32 (xv) and as a BF16 pair (dx: the same BF16 value in both
-// halves).  N must be a multiple of 4.
+// halves), and the spin bits of the row.  N must be a multiple of 4.
 template <int N>
-__device__ __forceinline__ void load_bfrag_s3(const int8_t* srow, const uint8_t* prow, int q,
-                                              bf16x8* bx, float* xv, uint32_t* dx) {
+__device__ __forceinline__ SpinBits load_bfrag_s3(const int8_t* srow, const uint8_t* prow, int q,
+                                                  bf16x8* bx, float* xv, uint32_t* dx) {
   static_assert(N % 4 == 0, "site-grouped fragments need N divisible by 4");
   constexpr int NI = N / 4, NM = nk_of<N, kPrecF32S3>();
   const SpinBits m = spin_bits<N>(srow);
@@ -215,6 +215,7 @@ __device__ __forceinline__ void load_bfrag_s3(const int8_t* srow, const uint8_t*
     }
     bx[mm] = __builtin_bit_cast(bf16x8, w);
   }
+  return m;
 }
 
 // The same fragments gathered byte by byte from the spin row (measured faster
