@@ -366,13 +366,20 @@ def leg_theta(m, sp, S, w, steps=3):
     out = torch.empty(S, dtype=torch.complex128, device="cuda")
     ms = timed(lambda: out.copy_(m.logpsi(sp)), steps, 1)
     flops = 4.0 * w.N * S * w.G * w.n_rbm * w.n_hidden
-    peak = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_FP32_MFMA_TFLOPS,
+    # FP32 models run theta on BF16 MFMA too (the exact three-term split of W,
+    # site-grouped: ceil(3 (N/4) / 8) 16x16x32 MFMAs per 16 x 16 tile); split
+    # BF16 takes ceil(2N / 32) (hi and lo halves of W), FP64 N/4 16x16x4 FP64
+    peak = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_BF16_MFMA_TFLOPS,
             "bf16x2": PEAK_BF16_MFMA_TFLOPS}[w.precision]
     km = kernel_ms(m, ("theta", "lse"), lambda: m.logpsi(sp), steps)
     t_ms = km["theta"][0] * km["theta"][1]
-    # split BF16 executes the contraction twice (hi and lo halves of W) over
-    # a K axis padded to a multiple of 32
-    executed = flops * (2 if w.precision == "bf16x2" else 1)
+    tiles = S * (w.G // 16) * (w.n_rbm * w.n_hidden // 8)
+    if w.precision == "fp32":
+        executed = tiles * -(-3 * (w.N // 4) // 8) * 16.0 * 16 * 32 * 2
+    elif w.precision == "bf16x2":
+        executed = tiles * -(-2 * w.N // 32) * 16.0 * 16 * 32 * 2
+    else:
+        executed = flops
     return {"precision": w.precision, "S": S, "ms": ms,
             "configs_sym_images_per_s": S * w.n_rbm * w.G / (ms / 1e3),
             "kernel_ms": {k: v[0] * v[1] for k, v in km.items()},

@@ -398,10 +398,10 @@ nqs_status nqs_create(const nqs_model_desc* d, nqs_ctx** out) {
   const size_t frag_bytes = (size_t)c->n_htiles * c->nk * 64 * (c->prec == NQS_BF16X2 ? 16 : rs);
   // FP32 models: theta from a three-term BF16 split of W, with the K axis as
   // [W_hi | W_mid | W_lo | 0] (wide E_loc and gradient kernels) and grouped
-  // by site (up to 6x6: theta kernel, fused E_loc and gradient kernels)
+  // by site (theta kernel, fused E_loc and gradient kernels)
   const size_t frag3_bytes =
       c->prec == NQS_FP32 ? (size_t)c->n_htiles * ((3 * c->N + 31) / 32) * 64 * 16 : 0;
-  const size_t frag_s3_bytes = c->prec == NQS_FP32 && c->N % 4 == 0 && c->N <= 36
+  const size_t frag_s3_bytes = c->prec == NQS_FP32 && c->N % 4 == 0
                                    ? (size_t)c->n_htiles * ((3 * (c->N / 4) + 7) / 8) * 64 * 16
                                    : 0;
   struct {

@@ -204,9 +204,10 @@ __global__ __launch_bounds__(256) void theta_kernel(
     }
     // Larger lattices (N > 36, longer MFMA chains per tile) software-pipeline
     // the tile loop: the next tile's MFMAs and fragment loads are issued before
-    // the current epilogue.  At N <= 36 the plain loop, with fewer live
-    // registers, is faster.
-    if constexpr (N <= 36) {
+    // the current epilogue.  At N <= 36, and for the site-grouped FP32 form at
+    // any N (short MFMA chains: 10 BF16 MFMAs a tile at N = 100), the plain
+    // loop, with fewer live registers, is faster.
+    if constexpr (N <= 36 || PREC == kPrecF32S3) {
       for (int tt = 0; tt < tiles_per_rbm; ++tt) {
         const int ht = k * tiles_per_rbm + tt;
         typename T::AFrag wf[NK];
@@ -432,10 +433,9 @@ hipError_t theta_prec(const nqs_ctx* c, const int8_t* spins, int64_t S, double* 
   switch (c->prec) {
     case NQS_FP64: return theta_for<N, NQS_FP64>(c, spins, S, Lout, t_out, st);
     // FP32 models: theta from the three-term BF16 split of W (FP32 numerics),
-    // site-grouped, up to 6x6; beyond, its longer fragment chains cost
-    // occupancy (the pipelined tile loop holds two tiles' fragments)
+    // site-grouped (at 8x8 and 10x10 2.1-2.4x faster than FP32 MFMA)
     case NQS_FP32:
-      if constexpr (N <= 36 && N % 4 == 0) return theta_for<N, kPrecF32S3>(c, spins, S, Lout, t_out, st);
+      if constexpr (N % 4 == 0) return theta_for<N, kPrecF32S3>(c, spins, S, Lout, t_out, st);
       else if constexpr (N <= 36) return theta_for<N, kPrecF32X3>(c, spins, S, Lout, t_out, st);
       else return theta_for<N, NQS_FP32>(c, spins, S, Lout, t_out, st);
     default: return theta_for<N, NQS_BF16X2>(c, spins, S, Lout, t_out, st);

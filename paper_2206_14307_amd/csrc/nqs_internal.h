@@ -70,7 +70,7 @@ struct ParamTables {
   double* params = nullptr;       // [P] complex double, caller layout
   void* wfrag = nullptr;          // MFMA A-operand fragments of the interleaved W
   void* wfrag3 = nullptr;         // FP32 models: BF16 fragments of [W_hi | W_mid | W_lo | 0]
-  void* wfrag_s3 = nullptr;       // FP32 models up to 6x6: site-grouped three-term fragments
+  void* wfrag_s3 = nullptr;       // FP32 models (N % 4 == 0): site-grouped three-term fragments
   void* bias = nullptr;           // [K*M] complex R (zeros without bias)
   void* avec = nullptr;           // [K][N] complex R
   void* Tpm = nullptr;            // [NB][2][K*M] complex R: +tanh(D), -tanh(D)
