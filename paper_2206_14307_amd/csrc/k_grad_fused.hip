@@ -42,6 +42,8 @@ struct GradCfg {
   static constexpr int NHT = KM / 8;             // hidden tiles: 8 units = 16 B columns
   static constexpr int NCT = NHT + 1;            // + the u tile (2K columns)
   static_assert(2 * K <= 4, "the u columns live in the 4 padding floats of a tile row");
+  // the output staging reuses the wave's tiles: 8 units x N complex, or K x N
+  static_assert(NHT * 16 * 20 >= 16 * N && NHT * 16 * 20 >= 2 * K * N, "output staging");
   static constexpr int NST = (N + 1 + 15) / 16;  // site tiles incl. the ones row
   static constexpr int NK = nk_of<N, PREC>();
   // one 16 x 16 tile, rows (images) 20 floats apart: the contraction's reads
