@@ -213,8 +213,12 @@ def test_larger_lattices(name, prec):
     sp = random_sz0_spins(w.N, 3, 5)
     m = make(w, p)
     glp, gel = m.eloc(cuda(sp))
-    assert max_logpsi_err(glp.cpu().numpy(), oracle.logpsi(om, p, sp)) < TOL[prec]
+    lref = oracle.logpsi(om, p, sp)
+    assert max_logpsi_err(glp.cpu().numpy(), lref) < TOL[prec]
     assert max_rel_err(gel.cpu().numpy(), oracle.eloc_direct(om, p, sp)) < TOL[prec]
+    # nqs_logpsi alone: the theta kernel (FP32 models: site-grouped three-term
+    # BF16 theta) and the log-sum-exp over the images
+    assert max_logpsi_err(m.logpsi(cuda(sp)).cpu().numpy(), lref) < TOL[prec]
 
 
 # ----------------------------------------------------------- sizes and edges
